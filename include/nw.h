@@ -1,0 +1,122 @@
+/*
+ * nw.h -- C ABI of libnw: all-pairs Needleman-Wunsch scoring on MI355X (gfx950).
+ *
+ * The operation is the global-alignment score of Algorithm 1 of Plein,
+ * "Parallel Needleman-Wunsch on CUDA to measure word similarity based on
+ * phonetic transcriptions" (2025), Section 2: the maximum, over all global
+ * alignments of words A and B, of the sum of similarity(A_x, B_y) over aligned
+ * symbol pairs plus the linear gap penalty p for every gap symbol (leading and
+ * trailing gaps included).  Words are integer-encoded symbol sequences
+ * (Section 3).  Every score is an exact integer.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Return value: NW_OK (0) or a negative status; nw_last_error() then holds a
+ *   thread-local message.  Argument errors are detected before anything is
+ *   enqueued.  Device errors reported by the HIP runtime surface as NW_EDEVICE.
+ * - Pointers named h_* are host memory; d_* are device memory of the current
+ *   HIP device; hip_stream is a hipStream_t (NULL = the null stream).
+ * - The caller owns every buffer.  The library never allocates device memory:
+ *   it works inside the memory (d_mem, d_ws) the caller hands in, whose sizes
+ *   the *_bytes queries give.  Host arrays may be reused as soon as a call
+ *   returns (the library copies what it needs before returning).
+ * - Calls enqueue kernels on hip_stream and return; results are valid once the
+ *   stream has been synchronised.  An nw_vocab must outlive every call that
+ *   uses it and every kernel those calls enqueued.
+ * - Word i is h_symbols[h_offsets[i] .. h_offsets[i+1]).  Lengths may be 0.
+ */
+#ifndef NW_H
+#define NW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NW_OK = 0,
+    NW_EINVAL = -1,   /* invalid argument (symbol >= alphabet, word too long, gap > 0, ...) */
+    NW_ERANGE = -2,   /* scores or DP values do not fit the requested/internal type       */
+    NW_ENOMEM = -3,   /* the memory handed in is smaller than the *_bytes query says       */
+    NW_EDEVICE = -4   /* the HIP runtime reported an error                                 */
+};
+
+typedef enum { NW_I8 = 1, NW_I16 = 2 } nw_dtype;
+
+/* Scoring of Algorithm 1: the similarity function and the gap penalty p.
+ * similarity(x, y) = submat[x * alphabet + y] if submat != NULL (host memory,
+ * copied at load), else match when x == y and mismatch otherwise.  x is a
+ * symbol of A (the row word), y a symbol of B.  gap is added once per gap
+ * symbol and must be <= 0 (Section 2 uses -2 in its examples, Section 4 uses
+ * -1 for every run). */
+typedef struct {
+    int32_t alphabet;        /* 1..255; every symbol must be < alphabet   */
+    int32_t match;           /* used when submat == NULL                  */
+    int32_t mismatch;        /* used when submat == NULL                  */
+    int32_t gap;             /* linear gap penalty p <= 0                 */
+    const int8_t *submat;    /* optional alphabet x alphabet, row-major   */
+} nw_scoring;
+
+/* Opaque handle to a device-resident dictionary (host-side descriptor). */
+typedef struct nw_vocab nw_vocab;
+
+/* Thread-local text of the last error (never NULL). */
+const char *nw_last_error(void);
+
+/* Longest word (symbols) the kernels accept. */
+int nw_max_word_length(void);
+
+/* Device bytes nw_load_vocab needs for n words holding total_symbols symbols,
+ * the longest being max_len.  NW_EINVAL if max_len exceeds the maximum. */
+int nw_vocab_bytes(uint64_t n, uint64_t total_symbols, uint32_t max_len, uint64_t *dev_bytes);
+
+/* Validate the words and the scoring, bucket the words by length (stable
+ * length sort inside fixed-size blocks of the caller's order) and copy the
+ * packed layout into d_mem (>= nw_vocab_bytes(...) bytes, 256-byte aligned).
+ * Synchronous: returns after the copy has completed on hip_stream.
+ * Errors: NW_EINVAL (n >= 2^31, a symbol >= alphabet, a word longer than
+ * nw_max_word_length(), gap > 0, alphabet outside 1..255), NW_ERANGE (the
+ * scores of these words could leave int16, or the DP could leave the range
+ * its 16-bit cells hold exactly), NW_ENOMEM (d_bytes too small).
+ * On success *out receives a handle to release with nw_free_vocab. */
+int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t n,
+                  const nw_scoring *sc, void *d_mem, uint64_t d_bytes, void *hip_stream,
+                  nw_vocab **out);
+
+/* Release the host descriptor (d_mem stays owned by the caller). */
+void nw_free_vocab(nw_vocab *v);
+
+/* n, the longest word, E = n(n-1)/2 unordered pairs and the number of DP
+ * cells sum over pairs of len(i)*len(j). Any out pointer may be NULL. */
+int nw_vocab_info(const nw_vocab *v, uint64_t *n, uint32_t *max_len, uint64_t *num_pairs,
+                  uint64_t *num_cells);
+
+/* Bounds every pair score of this dictionary lies in:
+ * lo = L * min(min similarity, p, 0), hi = L * max(max similarity, 0), L = longest word. */
+int nw_score_bounds(const nw_vocab *v, int32_t *lo, int32_t *hi);
+
+/* Scores of the unordered pairs (i, j), i < j, in the row-major order of the
+ * upper triangle of the adjacency matrix (Section 4.1):
+ * idx(i, j) = i(2n-i-1)/2 + (j-i-1), the forward form of the paper's S_{r-1}
+ * (Section 4.2).  Writes d_out[idx - idx_begin] = score(word i, word j) for
+ * every idx in [idx_begin, idx_end) -- the restartable chunk the paper
+ * proposes for going past device memory (Section 5).  d_out holds
+ * (idx_end - idx_begin) elements of dt (int8 or int16), row-major triangle
+ * order, in the caller's word order.
+ * Errors: NW_EINVAL (idx_begin > idx_end or idx_end > E, bad dtype),
+ * NW_ERANGE (the score bounds do not fit dt). */
+int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
+                        void *d_out, void *hip_stream);
+
+/* The same scores computed by the one-thread-per-pair scheme of Section 4.2
+ * (1-D grid, idx -> (row, column), one DP per thread).  Kept as the plain
+ * comparison point for the tiled kernels; same arguments and errors. */
+int nw_all_pairs_scores_naive(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
+                              void *d_out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NW_H */

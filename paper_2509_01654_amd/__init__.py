@@ -1,0 +1,156 @@
+"""Python binding of libnw (all-pairs Needleman-Wunsch scoring on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libnw.so`` behind the C ABI of ``include/nw.h``.  PyTorch provides
+device memory (the caller-owned buffers the library works in) and streams.
+There is no fallback: if the library has not been built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnw.so")
+
+NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOMEM, NW_EDEVICE = 0, -1, -2, -3, -4
+NW_I8, NW_I16 = 1, 2
+
+_lib = None
+
+
+class NwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libnw error {code}: {msg}")
+        self.code = code
+
+
+class _Scoring(ctypes.Structure):
+    _fields_ = [("alphabet", ctypes.c_int32), ("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap", ctypes.c_int32), ("submat", ctypes.c_void_p)]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnw.so (after torch, so both use the one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2509_01654_amd.build.build()")
+    try:
+        import torch  # noqa: F401  (binds libamdhip64 first)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    P, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+    sig = {
+        "nw_last_error": (ctypes.c_char_p, []),
+        "nw_max_word_length": (ctypes.c_int, []),
+        "nw_vocab_bytes": (ctypes.c_int, [u64, u64, u32, ctypes.POINTER(u64)]),
+        "nw_load_vocab": (ctypes.c_int, [P, P, u64, ctypes.POINTER(_Scoring), P, u64, P, ctypes.POINTER(P)]),
+        "nw_free_vocab": (None, [P]),
+        "nw_vocab_info": (ctypes.c_int, [P, ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u64),
+                                         ctypes.POINTER(u64)]),
+        "nw_score_bounds": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "nw_all_pairs_scores": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
+        "nw_all_pairs_scores_naive": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != NW_OK:
+        raise NwError(rc, _lib.nw_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def max_word_length() -> int:
+    return load_library().nw_max_word_length()
+
+
+def vocab_bytes(n: int, total_symbols: int, max_len: int) -> int:
+    lib = load_library()
+    out = ctypes.c_uint64()
+    _check(lib.nw_vocab_bytes(n, total_symbols, max_len, ctypes.byref(out)))
+    return out.value
+
+
+class Scoring:
+    """Similarity and gap penalty of Algorithm 1 (see nw_scoring in nw.h)."""
+
+    def __init__(self, alphabet: int, match: int = 1, mismatch: int = -1, gap: int = -1, submat=None):
+        self.alphabet, self.match, self.mismatch, self.gap = alphabet, match, mismatch, gap
+        self.submat = None if submat is None else np.ascontiguousarray(np.asarray(submat, dtype=np.int8))
+
+    def _c(self):
+        sp = self.submat.ctypes.data if self.submat is not None else None
+        return _Scoring(self.alphabet, self.match, self.mismatch, self.gap, sp)
+
+
+class Vocab:
+    """A dictionary resident on the current GPU (nw_load_vocab)."""
+
+    def __init__(self, symbols, offsets, scoring: Scoring, device="cuda", stream=None):
+        import torch
+        lib = load_library()
+        self.symbols = np.ascontiguousarray(np.asarray(symbols, dtype=np.uint8))
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        self.scoring = scoring
+        n = self.offsets.shape[0] - 1
+        lengths = np.diff(self.offsets)
+        max_len = int(lengths.max()) if n > 0 else 0
+        nbytes = vocab_bytes(n, int(self.offsets[-1]), max_len)
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        handle = ctypes.c_void_p()
+        sc = scoring._c()
+        _check(lib.nw_load_vocab(self.symbols.ctypes.data, self.offsets.ctypes.data, n, ctypes.byref(sc),
+                                 ctypes.c_void_p(self.mem.data_ptr()), nbytes, _stream_handle(stream),
+                                 ctypes.byref(handle)))
+        self._h = handle
+        self.device = self.mem.device
+        N, L, E, C = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib.nw_vocab_info(self._h, ctypes.byref(N), ctypes.byref(L), ctypes.byref(E), ctypes.byref(C)))
+        self.n, self.max_len, self.num_pairs, self.num_cells = N.value, L.value, E.value, C.value
+        lo, hi = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.nw_score_bounds(self._h, ctypes.byref(lo), ctypes.byref(hi)))
+        self.bounds = (lo.value, hi.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.nw_free_vocab(h)
+            self._h = None
+
+    def _triangle(self, fn, idx_begin, idx_end, dtype, out, stream):
+        import torch
+        if idx_end is None:
+            idx_end = self.num_pairs
+        dt = {torch.int8: NW_I8, torch.int16: NW_I16}[dtype]
+        if out is None:
+            out = torch.empty(max(0, idx_end - idx_begin), dtype=dtype, device=self.device)
+        assert out.dtype == dtype and out.is_contiguous() and out.numel() >= idx_end - idx_begin
+        _check(fn(self._h, idx_begin, idx_end, dt, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def all_pairs_scores(self, idx_begin: int = 0, idx_end: int | None = None, dtype=None, out=None, stream=None):
+        """Row-major upper-triangle scores for pair indices [idx_begin, idx_end)."""
+        import torch
+        return self._triangle(_lib.nw_all_pairs_scores, idx_begin, idx_end, dtype or torch.int8, out, stream)
+
+    def all_pairs_scores_naive(self, idx_begin: int = 0, idx_end: int | None = None, dtype=None, out=None,
+                               stream=None):
+        """Same output through the one-thread-per-pair kernel."""
+        import torch
+        return self._triangle(_lib.nw_all_pairs_scores_naive, idx_begin, idx_end, dtype or torch.int8, out, stream)

@@ -1,0 +1,75 @@
+"""Build libnw.so (HIP for gfx950) in-tree, one object per translation unit in parallel.
+
+Usage: python -m paper_2509_01654_amd.build   (or build() from Python)
+"""
+from __future__ import annotations
+
+import os
+import re
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libnw.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+DEVICE_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # packed fp32 VALU forms are kept out of every kernel
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def _tri_splits():
+    text = open(os.path.join(CSRC, "k_tri_tiled.h"), encoding="utf-8").read()
+    m = re.search(r"#define NW_TRI_SPLITS (.*)", text)
+    return [(int(a), int(b)) for a, b in re.findall(r"X\((\d+), (\d+)\)", m.group(1))]
+
+
+def _units():
+    units = [
+        ("nw_api", os.path.join(CSRC, "nw_api.cpp"), []),
+        ("k_triangle", os.path.join(CSRC, "k_triangle.hip"), []),
+    ]
+    for lo, hi in _tri_splits():
+        units.append((f"k_tri_inst_{lo}_{hi}", os.path.join(CSRC, "k_tri_inst.hip"),
+                      [f"-DNW_LA_LO={lo}", f"-DNW_LA_HI={hi}"]))
+    return units
+
+
+def _compile(unit):
+    name, src, extra = unit
+    obj = os.path.join(OUT_DIR, name + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [HIPCC] + DEVICE_FLAGS + extra + lang + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(jobs: int | None = None, verbose: bool = True) -> str:
+    """Compile every HIP/C++ unit for gfx950 and link libnw.so (always rebuilds)."""
+    os.makedirs(OUT_DIR, exist_ok=True)
+    units = _units()
+    jobs = jobs or min(len(units), max(1, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, units))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB} from {len(objs)} objects", file=sys.stderr)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()

@@ -1,0 +1,63 @@
+// nw_internal.h -- device layout of a loaded dictionary and the launchers the
+// C ABI calls.  Shared by the host runtime (nw_api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nw {
+
+// Longest word the kernels accept (the register-resident DP column of the
+// tiled kernel is unrolled per exact length up to this bound).
+constexpr int kMaxLen = 48;
+// Threads per workgroup of the tiled kernels (four wave64 wavefronts).
+constexpr int kThreads = 256;
+// Bytes of a padded word in the blocked layout (kMaxLen symbols, whole 16-byte loads).
+constexpr int kWordBytes = 48;
+// Profile entry of the sentinel symbol that pads lane words: -2048 in both
+// binary16 halves (0xE800 is the binary16 encoding of -2048).
+constexpr uint32_t kSentinelPair = 0xE800E800u;
+
+// The dictionary as the kernels see it.  All pointers are device memory inside
+// the caller's d_mem.
+//
+// Caller order: word u has length clen[u] and symbols csym[u*WB .. u*WB+len).
+// Blocked order: the words are cut into blocks of CB consecutive caller-order
+// words; inside each block they are sorted by length (stable).  Sorted slot
+// s (global: block*CB + local) holds the word whose caller index is
+// block*CB + bcol[s]; its symbols are bsym[s*WB ..] and its length blen[s]
+// (0 for the padding slots of the last block).
+// Row pairs: for block r and length L, rpairs[rp_off[r*(LMAX+1)+L] .. rp_off[..+1])
+// lists pairs of sorted slots of that block whose words both have length L
+// (second slot -1 when the count is odd).
+struct DevVocab {
+    const uint8_t *csym;
+    const uint8_t *clen;
+    const uint8_t *bsym;
+    const uint8_t *blen;
+    const uint16_t *bcol;
+    const int32_t *rpairs;      // [num_row_pairs][2]
+    const uint32_t *rp_off;     // [nb*(LMAX+1)+1]
+    const uint16_t *wtab;       // [alphabet*alphabet] binary16 bits of sim(x,y) - 2*gap
+    int64_t n;
+    int32_t nb;                 // number of blocks
+    int32_t CB;                 // block size (multiple of kThreads)
+    int32_t WB;                 // bytes per padded word (32 or 48)
+    int32_t lmax;               // LMAX of the rp_off table (longest word)
+    int32_t alphabet;
+    int32_t gap;
+    int32_t match, mismatch;    // plain +/- scoring when has_submat == 0
+    int32_t has_submat;
+    const int8_t *submat;       // [alphabet*alphabet] when has_submat
+};
+
+enum OutKind { OUT_I8 = 1, OUT_I16 = 2 };
+
+// Triangle launches.  Both enqueue on `stream` and return the hipError_t of
+// the launch.
+hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
+                                 void *d_out, hipStream_t stream);
+hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
+                                 void *d_out, hipStream_t stream);
+
+}  // namespace nw
