@@ -115,6 +115,42 @@ int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end,
 int nw_all_pairs_scores_naive(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
                               void *d_out, void *hip_stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Neighbour lists.  A neighbour of word i is ranked by (score descending,
+ * index ascending); identical words at different indices are distinct
+ * neighbours.  Lists shorter than k are padded with (INT16_MIN, -1).
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes nw_all_pairs_topk needs for this dictionary and k. */
+int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes);
+
+/* For every word i, its k best neighbours over all j != i (the self-loops the
+ * paper leaves out of the adjacency matrix, Section 4.1, are excluded here
+ * too): d_score[i*k + r] (int16) and d_index[i*k + r] (int32), r = 0..k-1.
+ * If d_hist != NULL it receives hi-lo+1 uint64 counts, bin b = number of
+ * unordered pairs {i, j} with score lo + b (bounds from nw_score_bounds): the
+ * histogram of raw edge weights of Section 5.  Every unordered pair is scored
+ * once.  d_ws: nw_topk_workspace_bytes() bytes, 256-byte aligned, caller-owned.
+ * Synchronous: returns once the results are complete on hip_stream.
+ * Errors: NW_EINVAL (k outside 1..63, asymmetric similarity), NW_ENOMEM
+ * (workspace too small). */
+int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist,
+                      void *d_ws, uint64_t ws_bytes, void *hip_stream);
+
+/* Workspace bytes nw_query needs for n_q query words (q_symbols is unused). */
+int nw_query_workspace_bytes(const nw_vocab *v, uint64_t n_q, uint64_t q_symbols, uint32_t k, uint64_t *bytes);
+
+/* For every query word q (host arrays in the same format as the dictionary),
+ * its k best dictionary neighbours over all dictionary words d (no
+ * self-exclusion), A = the query word: d_score[q*k + r], d_index[q*k + r].
+ * The similar-word lookup the paper envisions (Section 6).  Enqueued on
+ * hip_stream; the host arrays may be reused when the call returns.
+ * Errors: NW_EINVAL (k outside 1..64, bad query words), NW_ERANGE (query
+ * scores could leave int16), NW_ENOMEM (workspace too small). */
+int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_offsets, uint64_t n_q, uint32_t k,
+             int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,10 @@ def load_library(path: str = LIB_PATH):
         "nw_score_bounds": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "nw_all_pairs_scores": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
         "nw_all_pairs_scores_naive": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
+        "nw_topk_workspace_bytes": (ctypes.c_int, [P, u32, ctypes.POINTER(u64)]),
+        "nw_all_pairs_topk": (ctypes.c_int, [P, u32, P, P, P, P, u64, P]),
+        "nw_query_workspace_bytes": (ctypes.c_int, [P, u64, u64, u32, ctypes.POINTER(u64)]),
+        "nw_query": (ctypes.c_int, [P, P, P, u64, u32, P, P, P, u64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -154,3 +158,54 @@ class Vocab:
         """Same output through the one-thread-per-pair kernel."""
         import torch
         return self._triangle(_lib.nw_all_pairs_scores_naive, idx_begin, idx_end, dtype or torch.int8, out, stream)
+
+    # ------------------------------------------------------------------ top-k
+    def topk_workspace_bytes(self, k: int) -> int:
+        out = ctypes.c_uint64()
+        _check(_lib.nw_topk_workspace_bytes(self._h, k, ctypes.byref(out)))
+        return out.value
+
+    def all_pairs_topk(self, k: int = 32, hist: bool = True, ws=None, out=None, stream=None):
+        """Per-word top-k neighbours over all other words and the score histogram.
+
+        Returns (score int16 [n, k], index int32 [n, k], hist int64 [hi-lo+1] or None);
+        the histogram bin b counts unordered pairs with score lo + b.
+        """
+        import torch
+        nbytes = self.topk_workspace_bytes(k)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = (torch.empty((self.n, k), dtype=torch.int16, device=self.device),
+                   torch.empty((self.n, k), dtype=torch.int32, device=self.device),
+                   torch.empty(self.bounds[1] - self.bounds[0] + 1, dtype=torch.int64, device=self.device)
+                   if hist else None)
+        sc, ix, h = out
+        hp = ctypes.c_void_p(h.data_ptr()) if h is not None else None
+        _check(_lib.nw_all_pairs_topk(self._h, k, ctypes.c_void_p(sc.data_ptr()), ctypes.c_void_p(ix.data_ptr()), hp,
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+        return sc, ix, h
+
+    # ------------------------------------------------------------------ queries
+    def query_workspace_bytes(self, n_q: int, k: int) -> int:
+        out = ctypes.c_uint64()
+        _check(_lib.nw_query_workspace_bytes(self._h, n_q, 0, k, ctypes.byref(out)))
+        return out.value
+
+    def query(self, qsymbols, qoffsets, k: int = 16, ws=None, out=None, stream=None):
+        """Top-k dictionary neighbours of each query word: (score int16 [nq,k], index int32 [nq,k])."""
+        import torch
+        qsymbols = np.ascontiguousarray(np.asarray(qsymbols, dtype=np.uint8))
+        qoffsets = np.ascontiguousarray(np.asarray(qoffsets, dtype=np.uint64))
+        nq = qoffsets.shape[0] - 1
+        nbytes = self.query_workspace_bytes(nq, k)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int16, device=self.device),
+                   torch.empty((nq, k), dtype=torch.int32, device=self.device))
+        sc, ix = out
+        _check(_lib.nw_query(self._h, qsymbols.ctypes.data, qoffsets.ctypes.data, nq, k,
+                             ctypes.c_void_p(sc.data_ptr()), ctypes.c_void_p(ix.data_ptr()),
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+        return sc, ix

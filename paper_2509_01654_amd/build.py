@@ -25,19 +25,19 @@ DEVICE_FLAGS = [
 ]
 
 
-def _tri_splits():
-    text = open(os.path.join(CSRC, "k_tri_tiled.h"), encoding="utf-8").read()
-    m = re.search(r"#define NW_TRI_SPLITS (.*)", text)
+def _la_splits():
+    text = open(os.path.join(CSRC, "nw_kernels.h"), encoding="utf-8").read()
+    m = re.search(r"#define NW_LA_SPLITS (.*)", text)
     return [(int(a), int(b)) for a, b in re.findall(r"X\((\d+), (\d+)\)", m.group(1))]
 
 
 def _units():
     units = [
         ("nw_api", os.path.join(CSRC, "nw_api.cpp"), []),
-        ("k_triangle", os.path.join(CSRC, "k_triangle.hip"), []),
+        ("k_launch", os.path.join(CSRC, "k_launch.hip"), []),
     ]
-    for lo, hi in _tri_splits():
-        units.append((f"k_tri_inst_{lo}_{hi}", os.path.join(CSRC, "k_tri_inst.hip"),
+    for lo, hi in _la_splits():
+        units.append((f"k_inst_{lo}_{hi}", os.path.join(CSRC, "k_inst.hip"),
                       [f"-DNW_LA_LO={lo}", f"-DNW_LA_HI={hi}"]))
     return units
 

@@ -1,10 +1,14 @@
-// k_triangle.hip -- launchers of the triangle kernels, and the naive kernel.
+// k_launch.hip -- launchers of every kernel, and the naive triangle kernel.
 //
 // Naive kernel (k_tri_naive): the paper's GPU scheme (Section 4.2): one thread
 // per pair index, a 1-D grid, idx -> (row, column) through the closed form of
 // the row index, and one DP per thread with its scratch in shared memory (one
 // row of the score matrix instead of the whole matrix).
+#define NW_LAUNCH_TU 1
+#include "k_query.h"
+#include "k_topk.h"
 #include "k_tri_tiled.h"
+#include "nw_kernels.h"
 
 namespace nw {
 
@@ -52,21 +56,26 @@ __global__ __launch_bounds__(256) void k_tri_naive(DevVocab V, uint64_t idx_begi
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define X(lo, hi) void nw_tri_fill_##lo(tri_kernel_t *tab);
-NW_TRI_SPLITS
-#undef X
-
-static const tri_kernel_t *tiled_table()
+const KernelTables &kernel_tables()
 {
-    static tri_kernel_t tab[kMaxLen + 1];
+    static KernelTables t;
     static bool init = [] {
-#define X(lo, hi) nw_tri_fill_##lo(tab);
-        NW_TRI_SPLITS
+#define X(lo, hi) nw_fill_##lo(t);
+        NW_LA_SPLITS
 #undef X
         return true;
     }();
     (void)init;
-    return tab;
+    return t;
+}
+
+static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, hipStream_t stream, void **args)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipLaunchKernel(fn, grid, dim3(kThreads), args, lds, stream);
 }
 
 hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
@@ -74,20 +83,14 @@ hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     const uint32_t nblk_pairs = (uint32_t)((uint64_t)V.nb * (V.nb + 1) / 2);
-    const tri_kernel_t *tab = tiled_table();
+    const KernelTables &tab = kernel_tables();
     for (int LA = 0; LA <= V.lmax; ++LA) {
-        const size_t lds = tri_lds_bytes(LA, V.alphabet, V.CB);
-        const void *fn = reinterpret_cast<const void *>(tab[LA]);
-        if (lds > 65536) {
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-        }
         DevVocab Vc = V;
         uint64_t ib = idx_begin, ie = idx_end;
         void *po = d_out;
         int ok = out_kind;
         void *args[] = {&Vc, &ib, &ie, &po, &ok};
-        hipError_t e = hipLaunchKernel(fn, dim3(nblk_pairs), dim3(kThreads), args, lds, stream);
+        hipError_t e = launch_dyn(tab.tri[LA], dim3(nblk_pairs), tri_lds_bytes(LA, V.alphabet, V.CB), stream, args);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -106,6 +109,72 @@ hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t
     else
         hipLaunchKernelGGL(k_tri_naive<int16_t>, dim3(grid), dim3(256), 0, stream, V, idx_begin, idx_end,
                            (int16_t *)d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_off, const ColSet &C, int k,
+                        int nsplit, uint64_t *partial, hipStream_t stream)
+{
+    const KernelTables &tab = kernel_tables();
+    int64_t per = (C.nslots + nsplit - 1) / nsplit;
+    per = (per + kThreads - 1) / kThreads * kThreads;
+    const int rpw = 4;
+    for (int LA = 0; LA <= kMaxLen; ++LA) {
+        const uint32_t np = h_off[LA + 1] - h_off[LA];
+        if (np == 0) continue;
+        QueryArgs Q;
+        Q.R = R;
+        Q.C = C;
+        Q.wtab = V.wtab;
+        Q.alphabet = V.alphabet;
+        Q.gap = V.gap;
+        Q.lo = V.lo;
+        Q.k = k;
+        Q.rpw = rpw;
+        Q.per = per;
+        Q.nsplit = nsplit;
+        Q.partial = partial;
+        void *args[] = {&Q};
+        const dim3 grid((np + rpw - 1) / rpw, nsplit);
+        hipError_t e = launch_dyn(tab.query[LA], grid, query_lds_bytes(LA, V.alphabet), stream, args);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_merge(const uint64_t *partial, int P, int kin, int64_t rows, int kout, int lo, int16_t *score,
+                        int32_t *index, uint64_t *thr, int rank, hipStream_t stream)
+{
+    if (rows <= 0) return hipSuccess;
+    const uint32_t grid = (uint32_t)((rows + 3) / 4);
+    hipLaunchKernelGGL(k_merge_lists, dim3(grid), dim3(256), 0, stream, partial, P, kin, rows, kout, lo, score, index,
+                       thr, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t stream)
+{
+    if (V.n < 2) return hipSuccess;
+    const uint32_t nblk_pairs = (uint32_t)((uint64_t)V.nb * (V.nb + 1) / 2);
+    const KernelTables &tab = kernel_tables();
+    for (int LA = 0; LA <= V.lmax; ++LA) {
+        DevVocab Vc = V;
+        TopkArgs Tc = T;
+        void *args[] = {&Vc, &Tc};
+        hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs), topk_lds_bytes(LA, V.alphabet, T.nbins), stream,
+                                  args);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_select(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n, int k, int lo,
+                         int16_t *score, int32_t *index, uint32_t *ovf_count, int32_t *ovf_list, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const uint32_t grid = (uint32_t)((n + 3) / 4);
+    hipLaunchKernelGGL(k_select, dim3(grid), dim3(256), 0, stream, cnt, lists, cap, n, k, lo, score, index, ovf_count,
+                       ovf_list);
     return hipGetLastError();
 }
 

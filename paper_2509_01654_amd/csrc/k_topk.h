@@ -1,0 +1,147 @@
+// k_topk.h -- fused all-pairs top-k neighbour lists and score histogram.
+//
+// Every unordered pair {u, j} is scored once (block pairs (r, b), r <= b, as
+// in the triangle kernel) and offered to both endpoints: j to u's list and u
+// to j's list.  Each word w carries a threshold key thr[w] that is a lower
+// bound of its true k-th best key (the pre-pass computes it from the probe
+// subset), so only keys >= thr[w] can belong to w's answer; those are
+// appended to w's candidate list (cnt[w] counts every append, including any
+// past the capacity, so an overflow is detected).  The histogram counts every
+// unordered pair once, per integer score, in LDS and then globally.
+//
+// k_select: one wavefront per word keeps the best k of its candidates with a
+// wave list and writes the final (score, index) list; words whose candidate
+// count exceeded the capacity are reported for an exact recomputation.
+#pragma once
+
+#include "nw_tile_common.h"
+#include "nw_topk.h"
+
+namespace nw {
+
+struct TopkArgs {
+    const uint64_t *thr;        // [n] threshold keys
+    uint32_t *cnt;              // [n] candidate counters (zeroed)
+    uint64_t *lists;            // [n][cap]
+    uint32_t cap;
+    unsigned long long *hist;   // [nbins] or NULL
+    int lo;                     // lowest score (key and bin origin)
+    int nbins;
+};
+
+constexpr int kLdsHistMax = 4096;
+
+__host__ __device__ constexpr uint32_t topk_lds_bytes(int LA, int alphabet, int nbins)
+{
+    return 2u * profile_bytes(LA, alphabet) + 4u * (uint32_t)(nbins <= kLdsHistMax ? nbins : 0);
+}
+
+__device__ __forceinline__ void emit_candidate(const TopkArgs &T, int64_t w, uint64_t key)
+{
+    const uint32_t p = atomicAdd(&T.cnt[w], 1u);
+    if (p < T.cap) T.lists[w * (int64_t)T.cap + p] = key;
+}
+
+template <int LA>
+__global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t r, b;
+    decode_block_pair(blockIdx.x, r, b);
+    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
+    const uint32_t pbeg = rpo[0], pend = rpo[1];
+    if (pbeg >= pend) return;
+
+    const int64_t n = V.n, CB = V.CB;
+    const int64_t I0 = (int64_t)r * CB;
+    const int64_t J0 = (int64_t)b * CB;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const uint32_t prof_bytes = profile_bytes(LA, V.alphabet);
+    const bool lds_hist = T.hist != nullptr && T.nbins <= kLdsHistMax;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(lds + 2 * prof_bytes);
+    if (lds_hist)
+        for (int i = tid; i < T.nbins; i += kThreads) hist[i] = 0;
+    const ProfileRole role = profile_role(tid, V.alphabet);
+    const int CPL = V.CB / kThreads;
+
+    for (uint32_t k = pbeg; k < pend; ++k) {
+        const int32_t a0 = V.rpairs[2 * k], a1 = V.rpairs[2 * k + 1];
+        const uint8_t *prof = lds + (k & 1) * prof_bytes;
+        build_profile<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (k & 1) * prof_bytes),
+                          V.bsym + (int64_t)a0 * kWordBytes, V.bsym + (int64_t)(a1 >= 0 ? a1 : a0) * kWordBytes, role);
+        __syncthreads();
+        const int64_t u0 = I0 + V.bcol[a0];
+        const int64_t u1 = a1 >= 0 ? I0 + V.bcol[a1] : -1;
+        const uint64_t thr_u0 = T.thr[u0];
+        const uint64_t thr_u1 = u1 >= 0 ? T.thr[u1] : ~0ull;
+        for (int c = 0; c < CPL; ++c) {
+            const int64_t slot = J0 + (int64_t)(wave * 64 * CPL + c * 64 + lane);
+            const int lb = V.blen[slot];
+            const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);
+            int s0, s1;
+            pair_scores<LA>(V.bsym + slot * kWordBytes, lb, lbmax_w, prof, V.gap, s0, s1);
+            const int col = V.bcol[slot];
+            if (col == 0xFFFF) continue;
+            const int64_t j = J0 + col;
+            const uint64_t thr_j = T.thr[j];
+            // each unordered pair once: in a diagonal block only j > u
+            const bool v0 = (r < b) || (j > u0);
+            const bool v1 = u1 >= 0 && ((r < b) || (j > u1));
+            if (v0) {
+                if (lds_hist) atomicAdd(&hist[s0 - T.lo], 1u);
+                else if (T.hist) atomicAdd(&T.hist[s0 - T.lo], 1ull);
+                const uint64_t kr = nb_key(s0, T.lo, (uint32_t)j);
+                if (kr >= thr_u0) emit_candidate(T, u0, kr);
+                const uint64_t kc = nb_key(s0, T.lo, (uint32_t)u0);
+                if (kc >= thr_j) emit_candidate(T, j, kc);
+            }
+            if (v1) {
+                if (lds_hist) atomicAdd(&hist[s1 - T.lo], 1u);
+                else if (T.hist) atomicAdd(&T.hist[s1 - T.lo], 1ull);
+                const uint64_t kr = nb_key(s1, T.lo, (uint32_t)j);
+                if (kr >= thr_u1) emit_candidate(T, u1, kr);
+                const uint64_t kc = nb_key(s1, T.lo, (uint32_t)u1);
+                if (kc >= thr_j) emit_candidate(T, j, kc);
+            }
+        }
+    }
+    if (lds_hist) {
+        __syncthreads();
+        for (int i = tid; i < T.nbins; i += kThreads)
+            if (hist[i]) atomicAdd(&T.hist[i], (unsigned long long)hist[i]);
+    }
+}
+
+#ifdef NW_LAUNCH_TU   // non-template kernels: compiled in the launcher unit only
+// One wavefront per word: the best k of its (at most cap) candidates.
+// Words with more than cap candidates are appended to ovf_list.
+__global__ __launch_bounds__(256) void k_select(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n,
+                                                int k, int lo, int16_t *score, int32_t *index, uint32_t *ovf_count,
+                                                int32_t *ovf_list)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n) return;
+    const uint32_t c = cnt[w];
+    if (c > cap && lane == 0) {
+        const uint32_t p = atomicAdd(ovf_count, 1u);
+        ovf_list[p] = (int32_t)w;
+    }
+    const int m = (int)(c < cap ? c : cap);
+    const uint64_t *src = lists + w * (int64_t)cap;
+    uint64_t list = 0, t = 0;
+    for (int base = 0; base < m; base += 64) {
+        const int i = base + lane;
+        const uint64_t key = i < m ? src[i] : 0;
+        wl_offer(list, t, key, k, lane);
+    }
+    if (lane < k) {
+        score[w * k + lane] = list ? (int16_t)key_score(list, lo) : (int16_t)-32768;
+        index[w * k + lane] = list ? key_index(list) : -1;
+    }
+}
+
+#endif
+
+}  // namespace nw

@@ -6,17 +6,23 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "../../include/nw.h"
 #include "nw_internal.h"
+#include "k_topk.h"
 
 using namespace nw;
 
 struct nw_vocab {
     DevVocab dev;
+    std::vector<uint32_t> h_gp_off;   // host copy of dev.gp_off
+    std::vector<uint8_t> h_csym;      // host copy of the caller-order padded words
+    std::vector<uint8_t> h_clen;
+    int32_t smin = 0, smax = 0;       // similarity extremes
     uint64_t n = 0;
     uint32_t max_len = 0;
     uint64_t num_pairs = 0;
@@ -57,10 +63,15 @@ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 int choose_block(uint64_t n) { return n <= 16384 ? 256 : 1024; }
 
 
+// Probe subset of the top-k threshold pre-pass.
+constexpr uint64_t kMaxProbes = 16384;
+uint64_t num_probes(uint64_t n) { return n < kMaxProbes ? n : kMaxProbes; }
+
 // Byte offsets of every region inside d_mem.
 struct Layout {
-    uint64_t csym, clen, bsym, blen, bcol, rpairs, rp_off, wtab, submat, total;
+    uint64_t csym, clen, bsym, blen, bcol, rpairs, rp_off, wtab, submat, borig, gpairs, gp_off, psym, plen, porig, total;
     int CB, WB, nb;
+    uint64_t nprobe, pslots;
 };
 
 Layout make_layout(uint64_t n, uint32_t max_len)
@@ -86,6 +97,14 @@ Layout make_layout(uint64_t n, uint32_t max_len)
     L.rp_off = take(((uint64_t)L.nb * (kMaxLen + 1) + 1) * 4);
     L.wtab = take(256 * 256 * 2);
     L.submat = take(256 * 256);
+    L.borig = take(slots * 4);
+    L.gpairs = take(slots * 2 * 4);
+    L.gp_off = take((kMaxLen + 2) * 4);
+    L.nprobe = num_probes(n);
+    L.pslots = (L.nprobe + kThreads - 1) / kThreads * kThreads;
+    L.psym = take(L.pslots * L.WB);
+    L.plen = take(L.pslots);
+    L.porig = take(L.pslots * 4);
     L.total = o;
     return L;
 }
@@ -97,6 +116,138 @@ uint16_t f16_bits_of_int(int v)
     uint16_t b;
     std::memcpy(&b, &h, 2);
     return b;
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------- top-k
+struct TopkWs {
+    uint64_t thr, cnt, ovf, partial, lists, total;
+    uint32_t cap;
+};
+
+uint32_t topk_cap(uint64_t n, uint32_t k)
+{
+    // Expected candidates per word: the threshold is the (k+1)-th best key
+    // over M probe words, which ranks about (k+1)(n-1)/M among all n-1
+    // partners.  Twice that, plus a margin, bounds the list in practice; a
+    // word past the capacity is recomputed exactly.
+    const uint64_t M = num_probes(n);
+    double mean = M >= n ? (double)(k + 1) : (double)(k + 1) * (double)(n - 1) / (double)M;
+    uint64_t cap = (uint64_t)(2.0 * mean) + 64;
+    cap = (cap + 63) / 64 * 64;
+    const uint64_t most = (n + 63) / 64 * 64;
+    cap = std::max<uint64_t>(64, std::min(cap, most));
+    // NW_TOPK_CAP overrides the capacity (tests use it to force the
+    // overflow recomputation)
+    if (const char *env = std::getenv("NW_TOPK_CAP")) {
+        const long c = std::atol(env);
+        if (c > 0) cap = (uint64_t)c;
+    }
+    return (uint32_t)cap;
+}
+
+TopkWs topk_ws(uint64_t n, uint32_t k)
+{
+    TopkWs w{};
+    w.cap = topk_cap(n, k);
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + (bytes ? bytes : 1), 256);
+        return at;
+    };
+    w.thr = take(8 * n);
+    w.cnt = take(4 * n);
+    w.ovf = take(4 + 4 * n);
+    w.partial = take(8 * n * 4 * (uint64_t)(k + 1));
+    w.lists = take(8 * n * (uint64_t)w.cap);
+    w.total = o;
+    return w;
+}
+
+// ---------------------------------------------------------------- queries
+struct QueryWs {
+    uint64_t sym, pairs, off, orig, partial, total;
+    int nsplit;
+};
+
+int query_splits(uint64_t n_q)
+{
+    // enough workgroups to fill the GPU when few queries are in flight
+    const uint64_t pairs = (n_q + 1) / 2;
+    uint64_t s = pairs ? (2048 + pairs - 1) / pairs : 1;
+    return (int)std::min<uint64_t>(64, std::max<uint64_t>(1, s));
+}
+
+QueryWs query_ws(uint64_t n_q, uint32_t k)
+{
+    QueryWs w{};
+    w.nsplit = query_splits(n_q);
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + (bytes ? bytes : 1), 256);
+        return at;
+    };
+    w.sym = take(n_q * kWordBytes);
+    w.pairs = take((n_q + kMaxLen + 1) * 8);
+    w.off = take((kMaxLen + 2) * 4);
+    w.orig = take(n_q * 4);
+    w.partial = take(n_q * (uint64_t)w.nsplit * 4 * k * 8);
+    w.total = o;
+    return w;
+}
+
+// Host image of a row set: words sorted by length, paired by equal length.
+struct RowImage {
+    std::vector<uint8_t> sym;      // [m * kWordBytes]
+    std::vector<int32_t> pairs;    // [np * 2]
+    std::vector<uint32_t> off;     // [kMaxLen + 2]
+    std::vector<int32_t> orig;     // [m]
+};
+
+// words: (length, pointer to symbols, output row)
+RowImage make_rows(const std::vector<std::pair<int, std::pair<const uint8_t *, int32_t>>> &words)
+{
+    RowImage R;
+    const size_t m = words.size();
+    R.sym.assign(m * kWordBytes, 0);
+    R.orig.assign(m, -1);
+    R.off.assign(kMaxLen + 2, 0);
+    std::vector<size_t> order(m);
+    for (size_t i = 0; i < m; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return words[a].first < words[b].first; });
+    for (size_t s = 0; s < m; ++s) {
+        const auto &w = words[order[s]];
+        if (w.first) std::memcpy(&R.sym[s * kWordBytes], w.second.first, w.first);
+        R.orig[s] = w.second.second;
+    }
+    size_t s = 0;
+    for (int l = 0; l <= kMaxLen; ++l) {
+        R.off[l] = (uint32_t)(R.pairs.size() / 2);
+        size_t e = s;
+        while (e < m && words[order[e]].first == l) ++e;
+        for (size_t t = s; t < e; t += 2) {
+            R.pairs.push_back((int32_t)t);
+            R.pairs.push_back(t + 1 < e ? (int32_t)(t + 1) : -1);
+        }
+        s = e;
+    }
+    R.off[kMaxLen + 1] = (uint32_t)(R.pairs.size() / 2);
+    return R;
+}
+
+ColSet full_colset(const DevVocab &D)
+{
+    ColSet C;
+    C.sym = D.bsym;
+    C.len = D.blen;
+    C.orig = D.borig;
+    C.nslots = (int64_t)D.nb * D.CB;
+    return C;
 }
 
 }  // namespace
@@ -182,6 +333,13 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     std::vector<uint8_t> img(L.total, 0);
     // lane words are padded with the sentinel symbol (= alphabet)
     std::memset(img.data() + L.bsym, A, (size_t)L.nb * L.CB * L.WB);
+    std::memset(img.data() + L.psym, A, (size_t)L.pslots * L.WB);
+    int32_t *borig = reinterpret_cast<int32_t *>(img.data() + L.borig);
+    int32_t *gpairs = reinterpret_cast<int32_t *>(img.data() + L.gpairs);
+    uint32_t *gp_off = reinterpret_cast<uint32_t *>(img.data() + L.gp_off);
+    uint8_t *psym = img.data() + L.psym;
+    uint8_t *plen = img.data() + L.plen;
+    int32_t *porig = reinterpret_cast<int32_t *>(img.data() + L.porig);
     uint8_t *csym = img.data() + L.csym;
     uint8_t *clen = img.data() + L.clen;
     uint8_t *bsym = img.data() + L.bsym;
@@ -207,12 +365,13 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
         for (uint64_t u = u0; u < u1; ++u) by_len[clen[u]].push_back((int)(u - u0));
         // padding slots first (length 0, marked by column 0xFFFF), then real words by length
         uint64_t s = u0;
-        for (uint64_t p = u1; p < u0 + L.CB; ++p, ++s) { blen[s] = 0; bcol[s] = 0xFFFF; }
+        for (uint64_t p = u1; p < u0 + L.CB; ++p, ++s) { blen[s] = 0; bcol[s] = 0xFFFF; borig[s] = -1; }
         std::vector<uint64_t> slot_of(L.CB);
         for (int l = 0; l <= LM; ++l)
             for (int c : by_len[l]) {
                 blen[s] = (uint8_t)l;
                 bcol[s] = (uint16_t)c;
+                borig[s] = (int32_t)(u0 + c);
                 if (l) std::memcpy(bsym + s * L.WB, csym + (u0 + c) * L.WB, l);
                 slot_of[c] = s;
                 ++s;
@@ -228,6 +387,41 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
         }
     }
     rp_off[(size_t)L.nb * (LM + 1)] = npairs;
+    // the same row pairs grouped by length only
+    std::vector<uint32_t> h_gp_off(kMaxLen + 2, 0);
+    {
+        uint32_t g = 0;
+        for (int l = 0; l <= kMaxLen; ++l) {
+            h_gp_off[l] = g;
+            if (l <= LM)
+                for (int blk = 0; blk < L.nb; ++blk) {
+                    const uint32_t a = rp_off[(size_t)blk * (LM + 1) + l], b = rp_off[(size_t)blk * (LM + 1) + l + 1];
+                    for (uint32_t t = a; t < b; ++t, ++g) {
+                        gpairs[2 * g] = rpairs[2 * t];
+                        gpairs[2 * g + 1] = rpairs[2 * t + 1];
+                    }
+                }
+        }
+        h_gp_off[kMaxLen + 1] = g;
+        std::memcpy(gp_off, h_gp_off.data(), (kMaxLen + 2) * 4);
+    }
+    // probe subset: caller indices floor(i*n/M), sorted by length, padding slots first
+    {
+        std::vector<std::pair<int, int64_t>> pr;
+        for (uint64_t i = 0; i < L.nprobe; ++i) {
+            const int64_t u = (int64_t)(i * n / L.nprobe);
+            pr.push_back({clen[u], u});
+        }
+        std::stable_sort(pr.begin(), pr.end());
+        uint64_t s = 0;
+        for (; s < L.pslots - L.nprobe; ++s) { plen[s] = 0; porig[s] = -1; }
+        for (auto &e : pr) {
+            plen[s] = (uint8_t)e.first;
+            porig[s] = (int32_t)e.second;
+            if (e.first) std::memcpy(psym + s * L.WB, csym + e.second * L.WB, e.first);
+            ++s;
+        }
+    }
     for (int x = 0; x < A; ++x)
         for (int y = 0; y < A; ++y) {
             wtab[(size_t)x * A + y] = f16_bits_of_int(sim[(size_t)x * A + y] - 2 * sc->gap);
@@ -262,6 +456,21 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     D.match = sc->match;
     D.mismatch = sc->mismatch;
     D.has_submat = sc->submat ? 1 : 0;
+    D.borig = reinterpret_cast<const int32_t *>(base + L.borig);
+    D.gpairs = reinterpret_cast<const int32_t *>(base + L.gpairs);
+    D.gp_off = reinterpret_cast<const uint32_t *>(base + L.gp_off);
+    D.psym = base + L.psym;
+    D.plen = base + L.plen;
+    D.porig = reinterpret_cast<const int32_t *>(base + L.porig);
+    D.pslots = (int64_t)L.pslots;
+    D.nprobe = (int32_t)L.nprobe;
+    D.lo = (int32_t)lo;
+    D.hi = (int32_t)hi;
+    v->h_gp_off = h_gp_off;
+    v->h_csym.assign(csym, csym + n * L.WB);
+    v->h_clen.assign(clen, clen + n);
+    v->smin = smin;
+    v->smax = smax;
     v->n = n;
     v->max_len = max_len;
     v->num_pairs = n * (n ? n - 1 : 0) / 2;
@@ -328,6 +537,210 @@ int nw_all_pairs_scores_naive(const nw_vocab *v, uint64_t idx_begin, uint64_t id
     hipError_t e = launch_triangle_naive(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
                                          (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the naive triangle kernel");
+    return ok();
+}
+
+
+int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes)
+{
+    if (!v || !bytes) return fail(NW_EINVAL, "NULL argument");
+    if (k < 1 || k > 63) return fail(NW_EINVAL, "k = %u outside 1..63", k);
+    *bytes = topk_ws(v->n, k).total;
+    return ok();
+}
+
+int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist, void *d_ws,
+                      uint64_t ws_bytes, void *hip_stream)
+{
+    if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    if (k < 1 || k > 63) return fail(NW_EINVAL, "k = %u outside 1..63", k);
+    if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
+    const uint64_t n = v->n;
+    const TopkWs W = topk_ws(n, k);
+    if (n > 0 && (!d_score || !d_index)) return fail(NW_EINVAL, "d_score / d_index is NULL");
+    if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
+    if (ws_bytes < W.total)
+        return fail(NW_ENOMEM, "workspace holds %llu bytes; top-k needs %llu", (unsigned long long)ws_bytes,
+                    (unsigned long long)W.total);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const DevVocab &D = v->dev;
+    const int nbins = v->hi - v->lo + 1;
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    uint64_t *thr = reinterpret_cast<uint64_t *>(ws + W.thr);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(ws + W.cnt);
+    uint32_t *ovf = reinterpret_cast<uint32_t *>(ws + W.ovf);
+    uint64_t *partial = reinterpret_cast<uint64_t *>(ws + W.partial);
+    uint64_t *lists = reinterpret_cast<uint64_t *>(ws + W.lists);
+    hipError_t e;
+    if (d_hist && (e = hipMemsetAsync(d_hist, 0, (size_t)nbins * 8, st)) != hipSuccess) return dev_fail(e, "clearing the histogram");
+    if (n == 0) return ok();
+    if ((e = hipMemsetAsync(cnt, 0, 4 * n, st)) != hipSuccess) return dev_fail(e, "clearing counters");
+    if ((e = hipMemsetAsync(ovf, 0, 4, st)) != hipSuccess) return dev_fail(e, "clearing counters");
+
+    // 1. thresholds: each word's (k+1)-th best key over the probe subset
+    RowSet R;
+    R.sym = D.bsym;
+    R.pairs = D.gpairs;
+    R.off = D.gp_off;
+    R.orig = D.borig;
+    ColSet P;
+    P.sym = D.psym;
+    P.len = D.plen;
+    P.orig = D.porig;
+    P.nslots = D.pslots;
+    if ((e = launch_query(D, R, v->h_gp_off.data(), P, (int)k + 1, 1, partial, st)) != hipSuccess)
+        return dev_fail(e, "launching the threshold pre-pass");
+    if ((e = launch_merge(partial, 4, (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
+        return dev_fail(e, "launching the threshold merge");
+    // 2. every unordered pair once: candidates for both endpoints, histogram
+    TopkArgs T;
+    T.thr = thr;
+    T.cnt = cnt;
+    T.lists = lists;
+    T.cap = W.cap;
+    T.hist = reinterpret_cast<unsigned long long *>(d_hist);
+    T.lo = D.lo;
+    T.nbins = nbins;
+    if ((e = launch_topk_main(D, T, st)) != hipSuccess) return dev_fail(e, "launching the top-k main pass");
+    // 3. the best k of each word's candidates
+    if ((e = launch_select(cnt, lists, W.cap, (int64_t)n, (int)k, D.lo, d_score, d_index, ovf, reinterpret_cast<int32_t *>(ovf + 1), st)) != hipSuccess)
+        return dev_fail(e, "launching the top-k selection");
+    // 4. words whose candidates overflowed the list: exact recomputation
+    uint32_t novf = 0;
+    if ((e = hipMemcpyAsync(&novf, ovf, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return dev_fail(e, "reading the overflow count");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail(e, "top-k");
+    if (novf == 0) return ok();
+    std::vector<int32_t> words(novf);
+    if ((e = hipMemcpy(words.data(), ovf + 1, 4ull * novf, hipMemcpyDeviceToHost)) != hipSuccess) return dev_fail(e, "reading overflowed words");
+    // reuse the list area: rows (query image) then partial lists of k+1 keys
+    const int kq = (int)k + 1;
+    std::vector<std::pair<int, std::pair<const uint8_t *, int32_t>>> rows;
+    for (uint32_t t = 0; t < novf; ++t)
+        rows.push_back({v->h_clen[words[t]], {&v->h_csym[(size_t)words[t] * kWordBytes], (int32_t)t}});
+    RowImage img = make_rows(rows);
+    const int nsplit = 16;
+    const uint64_t need = align_up(img.sym.size(), 256) + align_up(img.pairs.size() * 4 + 8, 256) +
+                          align_up((kMaxLen + 2) * 4, 256) + align_up(img.orig.size() * 4, 256) +
+                          (uint64_t)novf * nsplit * 4 * kq * 8 + (uint64_t)novf * kq * 6;
+    if (need > 8 * n * (uint64_t)W.cap) return fail(NW_ENOMEM, "overflow recomputation does not fit the workspace");
+    uint8_t *q = reinterpret_cast<uint8_t *>(lists);
+    uint8_t *qsym = q; q += align_up(img.sym.size(), 256);
+    int32_t *qpairs = reinterpret_cast<int32_t *>(q); q += align_up(img.pairs.size() * 4 + 8, 256);
+    uint32_t *qoff = reinterpret_cast<uint32_t *>(q); q += align_up((kMaxLen + 2) * 4, 256);
+    int32_t *qorig = reinterpret_cast<int32_t *>(q); q += align_up(img.orig.size() * 4, 256);
+    uint64_t *qpart = reinterpret_cast<uint64_t *>(q); q += (uint64_t)novf * nsplit * 4 * kq * 8;
+    int16_t *qs = reinterpret_cast<int16_t *>(q);
+    int32_t *qi = reinterpret_cast<int32_t *>(ws + W.partial);
+    if ((e = hipMemcpy(qsym, img.sym.data(), img.sym.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(qpairs, img.pairs.data(), img.pairs.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(qoff, img.off.data(), img.off.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(qorig, img.orig.data(), img.orig.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return dev_fail(e, "uploading overflowed words");
+    RowSet QR;
+    QR.sym = qsym;
+    QR.pairs = qpairs;
+    QR.off = qoff;
+    QR.orig = qorig;
+    if ((e = launch_query(D, QR, img.off.data(), full_colset(D), kq, nsplit, qpart, st)) != hipSuccess ||
+        (e = launch_merge(qpart, nsplit * 4, kq, novf, kq, D.lo, qs, qi, nullptr, 1, st)) != hipSuccess)
+        return dev_fail(e, "launching the overflow recomputation");
+    std::vector<int16_t> hs((size_t)novf * kq);
+    std::vector<int32_t> hi((size_t)novf * kq);
+    if ((e = hipMemcpyAsync(hs.data(), qs, hs.size() * 2, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(hi.data(), qi, hi.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return dev_fail(e, "reading the overflow recomputation");
+    std::vector<int16_t> rs(k);
+    std::vector<int32_t> ri(k);
+    for (uint32_t t = 0; t < novf; ++t) {
+        const int32_t w = words[t];
+        uint32_t o = 0;
+        for (int c = 0; c < kq && o < k; ++c) {
+            if (hi[(size_t)t * kq + c] == w) continue;   // no self-loops
+            rs[o] = hs[(size_t)t * kq + c];
+            ri[o] = hi[(size_t)t * kq + c];
+            ++o;
+        }
+        for (; o < k; ++o) { rs[o] = -32768; ri[o] = -1; }
+        if ((e = hipMemcpy(d_score + (size_t)w * k, rs.data(), 2ull * k, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(d_index + (size_t)w * k, ri.data(), 4ull * k, hipMemcpyHostToDevice)) != hipSuccess)
+            return dev_fail(e, "writing the overflow recomputation");
+    }
+    return ok();
+}
+
+int nw_query_workspace_bytes(const nw_vocab *v, uint64_t n_q, uint64_t q_symbols, uint32_t k, uint64_t *bytes)
+{
+    (void)q_symbols;
+    if (!v || !bytes) return fail(NW_EINVAL, "NULL argument");
+    if (k < 1 || k > 64) return fail(NW_EINVAL, "k = %u outside 1..64", k);
+    *bytes = query_ws(n_q, k).total;
+    return ok();
+}
+
+int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_offsets, uint64_t n_q, uint32_t k,
+             int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes, void *hip_stream)
+{
+    if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    if (k < 1 || k > 64) return fail(NW_EINVAL, "k = %u outside 1..64", k);
+    if (n_q == 0) return ok();
+    if (!h_q_offsets || !d_score || !d_index) return fail(NW_EINVAL, "NULL argument");
+    if (n_q >= (1ull << 31)) return fail(NW_EINVAL, "n_q must be < 2^31");
+    const QueryWs W = query_ws(n_q, k);
+    if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
+    if (ws_bytes < W.total)
+        return fail(NW_ENOMEM, "workspace holds %llu bytes; the queries need %llu", (unsigned long long)ws_bytes,
+                    (unsigned long long)W.total);
+    const DevVocab &D = v->dev;
+    const int A = D.alphabet;
+    uint32_t qmax = 0;
+    if (h_q_offsets[0] != 0) return fail(NW_EINVAL, "query offsets[0] must be 0");
+    std::vector<std::pair<int, std::pair<const uint8_t *, int32_t>>> rows(n_q);
+    for (uint64_t i = 0; i < n_q; ++i) {
+        if (h_q_offsets[i + 1] < h_q_offsets[i]) return fail(NW_EINVAL, "query offsets decrease at %llu", (unsigned long long)i);
+        const uint64_t l = h_q_offsets[i + 1] - h_q_offsets[i];
+        if (l > (uint64_t)kMaxLen) return fail(NW_EINVAL, "query %llu has %llu symbols; the maximum is %d", (unsigned long long)i, (unsigned long long)l, kMaxLen);
+        for (uint64_t t = 0; t < l; ++t)
+            if (h_q_symbols[h_q_offsets[i] + t] >= A) return fail(NW_EINVAL, "query %llu has a symbol >= alphabet", (unsigned long long)i);
+        qmax = std::max<uint32_t>(qmax, (uint32_t)l);
+        rows[i] = {(int)l, {h_q_symbols + h_q_offsets[i], (int32_t)i}};
+    }
+    // scores of a query pair lie in [max(lq, ld) * min(smin, p, 0), min(lq, ld) * max(smax, 0)]
+    const long L = std::max<long>(qmax, v->max_len);
+    const long lo = std::min<long>(D.lo, L * std::min({(long)v->smin, (long)D.gap, 0L}));
+    if (lo < -32768) return fail(NW_ERANGE, "query scores may fall below int16");
+    RowImage img = make_rows(rows);
+    // one contiguous host image of the row set -> one copy; the image lives
+    // until the copy has completed (freed by a host callback on the stream)
+    auto *host = new std::vector<uint8_t>(W.partial, 0);
+    std::memcpy(host->data() + W.sym, img.sym.data(), img.sym.size());
+    std::memcpy(host->data() + W.pairs, img.pairs.data(), img.pairs.size() * 4);
+    std::memcpy(host->data() + W.off, img.off.data(), img.off.size() * 4);
+    std::memcpy(host->data() + W.orig, img.orig.data(), img.orig.size() * 4);
+    hipStream_t st = (hipStream_t)hip_stream;
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    hipError_t e = hipMemcpyAsync(ws, host->data(), host->size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        delete host;
+        return dev_fail(e, "uploading queries");
+    }
+    e = hipLaunchHostFunc(st, [](void *p) { delete static_cast<std::vector<uint8_t> *>(p); }, host);
+    if (e != hipSuccess) {
+        hipStreamSynchronize(st);
+        delete host;
+        return dev_fail(e, "scheduling the release of the query staging buffer");
+    }
+    RowSet R;
+    R.sym = ws + W.sym;
+    R.pairs = reinterpret_cast<const int32_t *>(ws + W.pairs);
+    R.off = reinterpret_cast<const uint32_t *>(ws + W.off);
+    R.orig = reinterpret_cast<const int32_t *>(ws + W.orig);
+    DevVocab Dq = D;
+    Dq.lo = (int32_t)lo;
+    uint64_t *partial = reinterpret_cast<uint64_t *>(ws + W.partial);
+    if ((e = launch_query(Dq, R, img.off.data(), full_colset(D), (int)k, W.nsplit, partial, st)) != hipSuccess ||
+        (e = launch_merge(partial, W.nsplit * 4, (int)k, (int64_t)n_q, (int)k, (int)lo, d_score, d_index, nullptr, 1, st)) != hipSuccess)
+        return dev_fail(e, "launching the query kernels");
     return ok();
 }
 

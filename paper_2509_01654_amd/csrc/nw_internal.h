@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "nw_topk.h"
+
 namespace nw {
 
 // Longest word the kernels accept (the register-resident DP column of the
@@ -29,7 +31,11 @@ constexpr uint32_t kSentinelPair = 0xE800E800u;
 // (0 for the padding slots of the last block).
 // Row pairs: for block r and length L, rpairs[rp_off[r*(LMAX+1)+L] .. rp_off[..+1])
 // lists pairs of sorted slots of that block whose words both have length L
-// (second slot -1 when the count is odd).
+// (second slot -1 when the count is odd).  gpairs holds the same pairs grouped
+// by length only: gpairs[gp_off[L] .. gp_off[L+1]).
+// borig[s] is the caller index of slot s (-1 for padding slots).
+// Probe subset (threshold pre-pass of the top-k): nprobe words at caller
+// indices floor(i*n/nprobe), sorted by length, as a column set of pslots slots.
 struct DevVocab {
     const uint8_t *csym;
     const uint8_t *clen;
@@ -49,15 +55,46 @@ struct DevVocab {
     int32_t match, mismatch;    // plain +/- scoring when has_submat == 0
     int32_t has_submat;
     const int8_t *submat;       // [alphabet*alphabet] when has_submat
+    const int32_t *borig;       // [nb*CB]
+    const int32_t *gpairs;      // [num_row_pairs][2]
+    const uint32_t *gp_off;     // [kMaxLen+2]
+    const uint8_t *psym;        // probe words [pslots*WB]
+    const uint8_t *plen;        // [pslots]
+    const int32_t *porig;       // [pslots]
+    int64_t pslots;
+    int32_t nprobe;
+    int32_t lo, hi;             // score bounds
 };
 
 enum OutKind { OUT_I8 = 1, OUT_I16 = 2 };
 
-// Triangle launches.  Both enqueue on `stream` and return the hipError_t of
-// the launch.
+// Launchers.  Each enqueues on `stream` and returns the hipError_t of the
+// launches.
+
+// Triangle scores of pair indices [idx_begin, idx_end).
 hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
                                  void *d_out, hipStream_t stream);
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
                                  void *d_out, hipStream_t stream);
+
+// Per-row top-k lists of the rows R (pairs grouped by length, h_off = host
+// copy of R.off) against the column set C, split over nsplit column ranges:
+// partial[row][nsplit*4][k].  Scoring from V.
+hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_off, const ColSet &C, int k,
+                        int nsplit, uint64_t *partial, hipStream_t stream);
+
+// Merge partial lists [rows][P][kin] into the top kout (scores/indices
+// and/or the key of rank `rank`).
+hipError_t launch_merge(const uint64_t *partial, int P, int kin, int64_t rows, int kout, int lo, int16_t *score,
+                        int32_t *index, uint64_t *thr, int rank, hipStream_t stream);
+
+// Main pass of the all-pairs top-k: candidates >= thr into per-word lists,
+// plus the histogram.
+struct TopkArgs;
+hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t stream);
+
+// Final per-word selection from the candidate lists.
+hipError_t launch_select(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n, int k, int lo,
+                         int16_t *score, int32_t *index, uint32_t *ovf_count, int32_t *ovf_list, hipStream_t stream);
 
 }  // namespace nw
