@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the all-pairs Needleman-Wunsch hot path on one MI355X.
+
+Default workload (the paper's scale): 600,000 synthetic words (40-symbol
+Zipf(1.1) alphabet, lengths clip(Poisson(8), 1, 32)), scoring +1/-1, gap -1;
+one step = the whole all-pairs pass producing every word's top-32 neighbours
+(int16 score, int32 index, ties by lower index) and the global score
+histogram: n(n-1)/2 = 1.8e11 pairs, every pair scored once.
+
+    python bench.py [--steps K] [--warmup W] [--workload paper|mid] [--cpu-seconds S]
+
+Prints one JSON line (see the design doc for every field).  --gpus N with N > 1
+exits: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "all-pairs NW GCUPS + pairs/s at 600k words; served query p50/p99 latency"
+# nominal packed 16-bit VALU peak of MI355X: 256 CUs x 64 lanes x 2 halves x 2.4 GHz
+PEAK_16BIT_OPS = 256 * 64 * 2 * 2.4e9
+OPS_PER_CELL = 5            # 2 adds, 2 maxes, 1 similarity per DP cell (Algorithm 1)
+
+
+def host_cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(v, k, gpu_scores, gpu_index, budget_s):
+    """The oracle on a bounded sample of rows (each row: all n-1 partners).
+
+    Returns the baseline record and whether the sampled rows match the GPU."""
+    import numpy as np
+    import oracle
+    threads = oracle.default_threads()
+    sim = oracle.sim_matrix(v.alphabet, 1, -1)
+    L = v.lengths
+    total_l = int(L.sum())
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(v.n)
+    done, cells, t_used, ok = 0, 0, 0.0, True
+    while t_used < budget_s and done < v.n:
+        rows = order[done:done + threads]
+        t0 = time.perf_counter()
+        # the oracle splits rows over its threads; one row per call runs single-threaded,
+        # so a batch of `threads` single-row calls runs side by side
+        res = [None] * len(rows)
+        with cf.ThreadPoolExecutor(max_workers=len(rows)) as ex:
+            futs = {ex.submit(oracle.topk_rows, v.symbols, v.offsets, sim, -1, k, int(r), int(r) + 1, None, 1): t
+                    for t, r in enumerate(rows)}
+            for f in cf.as_completed(futs):
+                res[futs[f]] = f.result()
+        t_used += time.perf_counter() - t0
+        for t, r in enumerate(rows):
+            ws, wi, _ = res[t]
+            ok &= bool((gpu_index[r] == wi[0]).all() and (gpu_scores[r] == ws[0]).all())
+            cells += int(L[r]) * (total_l - int(L[r]))
+        done += len(rows)
+    rec = {"value": cells / t_used / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{done} random rows x all {v.n - 1} partners each (top-{k} by full sort), "
+                     f"{cells:.3e} cells in {t_used:.1f} s on {host_cpu_model()}",
+           "pairs_per_s": done * (v.n - 1) / t_used}
+    return rec, ok, done
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["paper", "mid"], default="paper")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2509_01654_amd as nw
+    import synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    v = synth.plain_config(args.workload)
+    dv = nw.Vocab(v.symbols, v.offsets, nw.Scoring(40, 1, -1, -1), device=dev)
+    E, cells = dv.num_pairs, dv.num_cells
+    k = 32
+    stream = torch.cuda.current_stream()
+
+    if args.workload == "paper":
+        ws = torch.empty(dv.topk_workspace_bytes(k), dtype=torch.uint8, device=dev)
+        out = (torch.empty((dv.n, k), dtype=torch.int16, device=dev),
+               torch.empty((dv.n, k), dtype=torch.int32, device=dev),
+               torch.empty(dv.bounds[1] - dv.bounds[0] + 1, dtype=torch.int64, device=dev))
+
+        def step():
+            dv.all_pairs_topk(k, ws=ws, out=out)
+    else:
+        tri = torch.empty(E, dtype=torch.int8, device=dev)
+
+        def step():
+            dv.all_pairs_scores(dtype=torch.int8, out=tri)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    phases = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+        if args.workload == "paper":
+            phases.append(dv.topk_phase_times())
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = cells / (ms_per_step / 1e3) / 1e9
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "pairs_per_s": E / (ms_per_step / 1e3),
+    }
+    if args.workload == "paper":
+        pre, main_ms, sel = (float(np.mean([p[i] for p in phases])) for i in range(3))
+        rec["config"] = {"workload": "all-pairs top-32 neighbours + score histogram, 600,000 words "
+                                     "(Zipf-40, clip(Poisson 8, 1, 32), +1/-1, gap -1)",
+                         "n_words": dv.n, "k": k, "pairs": E, "cells": cells}
+        rec["phase_ms"] = {"threshold_prepass": round(pre, 3), "main_pass": round(main_ms, 3),
+                           "select": round(sel, 3)}
+        achieved = OPS_PER_CELL * cells / (main_ms / 1e3)
+        rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
+                           "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
+                           "kernel": "k_topk_tiled (all-pairs main pass, every LA)"}
+        sc, ix, h = out
+        hist = h.cpu().numpy()
+        assert int(hist.sum()) == E, "histogram does not count every pair once"
+        if not args.no_cpu:
+            cb, ok, rows = cpu_baseline(v, k, sc.cpu().numpy().astype(np.int32), ix.cpu().numpy(), args.cpu_seconds)
+            rec["cpu_baseline"] = cb
+            rec["parity_sample"] = {"rows": rows, "bit_exact": ok}
+    else:
+        rec["config"] = {"workload": "all-pairs int8 triangle, 50,000 words (Zipf-40, clip(Poisson 7, 1, 20), "
+                                     "+1/-1, gap -1)", "n_words": dv.n, "pairs": E, "cells": cells}
+        achieved = OPS_PER_CELL * cells / (ms_per_step / 1e3)
+        rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
+                           "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
+                           "kernel": "k_tri_tiled (every LA)"}
+        rec["output_GB_per_s"] = E / (ms_per_step / 1e3) / 1e9
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,12 @@ int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes);
 int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist,
                       void *d_ws, uint64_t ws_bytes, void *hip_stream);
 
+/* GPU time of the three phases of the last completed nw_all_pairs_topk call
+ * on this dictionary, from HIP events recorded on its stream: the probe
+ * threshold pre-pass, the all-pairs main pass, and the per-word selection
+ * (milliseconds; any pointer may be NULL). */
+int nw_topk_phase_times(const nw_vocab *v, float *prepass_ms, float *main_ms, float *select_ms);
+
 /* Workspace bytes nw_query needs for n_q query words (q_symbols is unused). */
 int nw_query_workspace_bytes(const nw_vocab *v, uint64_t n_q, uint64_t q_symbols, uint32_t k, uint64_t *bytes);
 

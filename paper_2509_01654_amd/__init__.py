@@ -59,6 +59,8 @@ def load_library(path: str = LIB_PATH):
         "nw_topk_workspace_bytes": (ctypes.c_int, [P, u32, ctypes.POINTER(u64)]),
         "nw_all_pairs_topk": (ctypes.c_int, [P, u32, P, P, P, P, u64, P]),
         "nw_query_workspace_bytes": (ctypes.c_int, [P, u64, u64, u32, ctypes.POINTER(u64)]),
+        "nw_topk_phase_times": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                               ctypes.POINTER(ctypes.c_float)]),
         "nw_query": (ctypes.c_int, [P, P, P, u64, u32, P, P, P, u64, P]),
     }
     for name, (res, args) in sig.items():
@@ -185,6 +187,12 @@ class Vocab:
         _check(_lib.nw_all_pairs_topk(self._h, k, ctypes.c_void_p(sc.data_ptr()), ctypes.c_void_p(ix.data_ptr()), hp,
                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
         return sc, ix, h
+
+    def topk_phase_times(self):
+        """(pre-pass, main pass, select) GPU milliseconds of the last all_pairs_topk."""
+        a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _check(_lib.nw_topk_phase_times(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     # ------------------------------------------------------------------ queries
     def query_workspace_bytes(self, n_q: int, k: int) -> int:

@@ -23,6 +23,14 @@ struct nw_vocab {
     std::vector<uint8_t> h_csym;      // host copy of the caller-order padded words
     std::vector<uint8_t> h_clen;
     int32_t smin = 0, smax = 0;       // similarity extremes
+    // phase timing of the last top-k call (HIP events on the caller's stream)
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    float phase_ms[3] = {0, 0, 0};
+    ~nw_vocab()
+    {
+        for (auto &e : ev)
+            if (e) hipEventDestroy(e);
+    }
     uint64_t n = 0;
     uint32_t max_len = 0;
     uint64_t num_pairs = 0;
@@ -577,6 +585,10 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     if ((e = hipMemsetAsync(cnt, 0, 4 * n, st)) != hipSuccess) return dev_fail(e, "clearing counters");
     if ((e = hipMemsetAsync(ovf, 0, 4, st)) != hipSuccess) return dev_fail(e, "clearing counters");
 
+    nw_vocab *vm = const_cast<nw_vocab *>(v);
+    for (auto &ev : vm->ev)
+        if (!ev && (e = hipEventCreate(&ev)) != hipSuccess) return dev_fail(e, "creating timing events");
+    if ((e = hipEventRecord(vm->ev[0], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 1. thresholds: each word's (k+1)-th best key over the probe subset
     RowSet R;
     R.sym = D.bsym;
@@ -592,6 +604,7 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
         return dev_fail(e, "launching the threshold pre-pass");
     if ((e = launch_merge(partial, 4, (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
         return dev_fail(e, "launching the threshold merge");
+    if ((e = hipEventRecord(vm->ev[1], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 2. every unordered pair once: candidates for both endpoints, histogram
     TopkArgs T;
     T.thr = thr;
@@ -602,13 +615,18 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     T.lo = D.lo;
     T.nbins = nbins;
     if ((e = launch_topk_main(D, T, st)) != hipSuccess) return dev_fail(e, "launching the top-k main pass");
+    if ((e = hipEventRecord(vm->ev[2], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 3. the best k of each word's candidates
     if ((e = launch_select(cnt, lists, W.cap, (int64_t)n, (int)k, D.lo, d_score, d_index, ovf, reinterpret_cast<int32_t *>(ovf + 1), st)) != hipSuccess)
         return dev_fail(e, "launching the top-k selection");
+    if ((e = hipEventRecord(vm->ev[3], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 4. words whose candidates overflowed the list: exact recomputation
     uint32_t novf = 0;
     if ((e = hipMemcpyAsync(&novf, ovf, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return dev_fail(e, "reading the overflow count");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail(e, "top-k");
+    for (int ph = 0; ph < 3; ++ph)
+        if ((e = hipEventElapsedTime(&vm->phase_ms[ph], vm->ev[ph], vm->ev[ph + 1])) != hipSuccess)
+            return dev_fail(e, "reading timing events");
     if (novf == 0) return ok();
     std::vector<int32_t> words(novf);
     if ((e = hipMemcpy(words.data(), ovf + 1, 4ull * novf, hipMemcpyDeviceToHost)) != hipSuccess) return dev_fail(e, "reading overflowed words");
@@ -666,6 +684,15 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
             (e = hipMemcpy(d_index + (size_t)w * k, ri.data(), 4ull * k, hipMemcpyHostToDevice)) != hipSuccess)
             return dev_fail(e, "writing the overflow recomputation");
     }
+    return ok();
+}
+
+int nw_topk_phase_times(const nw_vocab *v, float *prepass_ms, float *main_ms, float *select_ms)
+{
+    if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    if (prepass_ms) *prepass_ms = v->phase_ms[0];
+    if (main_ms) *main_ms = v->phase_ms[1];
+    if (select_ms) *select_ms = v->phase_ms[2];
     return ok();
 }
 
