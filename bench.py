@@ -30,6 +30,8 @@ METRIC = "all-pairs NW GCUPS + pairs/s at 600k words; served query p50/p99 laten
 # nominal packed 16-bit VALU peak of MI355X: 256 CUs x 64 lanes x 2 halves x 2.4 GHz
 PEAK_16BIT_OPS = 256 * 64 * 2 * 2.4e9
 OPS_PER_CELL = 5            # 2 adds, 2 maxes, 1 similarity per DP cell (Algorithm 1)
+# VALU issue ceiling of the kernel's instruction sequence: one lane-instruction per cell
+PEAK_ISSUE_CELLS = 256 * 64 * 2.4e9
 
 
 def host_cpu_model() -> str:
@@ -165,7 +167,8 @@ def main():
         achieved = OPS_PER_CELL * cells / (main_ms / 1e3)
         rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
                            "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
-                           "kernel": "k_topk_tiled (all-pairs main pass, every LA)"}
+                           "kernel": "k_topk_tiled (all-pairs main pass, every LA)",
+                           "issue_frac": round(cells / (main_ms / 1e3) / PEAK_ISSUE_CELLS, 4)}
         sc, ix, h = out
         hist = h.cpu().numpy()
         assert int(hist.sum()) == E, "histogram does not count every pair once"
@@ -179,7 +182,8 @@ def main():
         achieved = OPS_PER_CELL * cells / (ms_per_step / 1e3)
         rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
                            "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
-                           "kernel": "k_tri_tiled (every LA)"}
+                           "kernel": "k_tri_tiled (every LA)",
+                           "issue_frac": round(cells / (ms_per_step / 1e3) / PEAK_ISSUE_CELLS, 4)}
         rec["output_GB_per_s"] = E / (ms_per_step / 1e3) / 1e9
     print(json.dumps(rec), flush=True)
 

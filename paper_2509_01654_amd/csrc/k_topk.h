@@ -75,6 +75,9 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
         const int64_t u1 = a1 >= 0 ? I0 + V.bcol[a1] : -1;
         const uint64_t thr_u0 = T.thr[u0];
         const uint64_t thr_u1 = u1 >= 0 ? T.thr[u1] : ~0ull;
+        // a key >= thr needs score >= the threshold's score: test that first
+        const int ts_u0 = key_score(thr_u0, T.lo);
+        const int ts_u1 = key_score(thr_u1, T.lo);
         for (int c = 0; c < CPL; ++c) {
             const int64_t slot = J0 + (int64_t)(wave * 64 * CPL + c * 64 + lane);
             const int lb = V.blen[slot];
@@ -85,24 +88,33 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
             if (col == 0xFFFF) continue;
             const int64_t j = J0 + col;
             const uint64_t thr_j = T.thr[j];
+            const int ts_j = key_score(thr_j, T.lo);
             // each unordered pair once: in a diagonal block only j > u
             const bool v0 = (r < b) || (j > u0);
             const bool v1 = u1 >= 0 && ((r < b) || (j > u1));
             if (v0) {
                 if (lds_hist) atomicAdd(&hist[s0 - T.lo], 1u);
                 else if (T.hist) atomicAdd(&T.hist[s0 - T.lo], 1ull);
-                const uint64_t kr = nb_key(s0, T.lo, (uint32_t)j);
-                if (kr >= thr_u0) emit_candidate(T, u0, kr);
-                const uint64_t kc = nb_key(s0, T.lo, (uint32_t)u0);
-                if (kc >= thr_j) emit_candidate(T, j, kc);
+                if (s0 >= ts_u0) {
+                    const uint64_t kr = nb_key(s0, T.lo, (uint32_t)j);
+                    if (kr >= thr_u0) emit_candidate(T, u0, kr);
+                }
+                if (s0 >= ts_j) {
+                    const uint64_t kc = nb_key(s0, T.lo, (uint32_t)u0);
+                    if (kc >= thr_j) emit_candidate(T, j, kc);
+                }
             }
             if (v1) {
                 if (lds_hist) atomicAdd(&hist[s1 - T.lo], 1u);
                 else if (T.hist) atomicAdd(&T.hist[s1 - T.lo], 1ull);
-                const uint64_t kr = nb_key(s1, T.lo, (uint32_t)j);
-                if (kr >= thr_u1) emit_candidate(T, u1, kr);
-                const uint64_t kc = nb_key(s1, T.lo, (uint32_t)u1);
-                if (kc >= thr_j) emit_candidate(T, j, kc);
+                if (s1 >= ts_u1) {
+                    const uint64_t kr = nb_key(s1, T.lo, (uint32_t)j);
+                    if (kr >= thr_u1) emit_candidate(T, u1, kr);
+                }
+                if (s1 >= ts_j) {
+                    const uint64_t kc = nb_key(s1, T.lo, (uint32_t)u1);
+                    if (kc >= thr_j) emit_candidate(T, j, kc);
+                }
             }
         }
     }

@@ -68,7 +68,14 @@ int dev_fail(hipError_t e, const char *what)
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-int choose_block(uint64_t n) { return n <= 16384 ? 256 : 1024; }
+// Block size: small dictionaries need many workgroups; large ones amortise
+// the per-row-pair work (profile build, barrier) over more lane words.
+int choose_block(uint64_t n)
+{
+    if (n <= 16384) return 256;
+    if (n <= 131072) return 1024;
+    return 2048;
+}
 
 
 // Probe subset of the top-k threshold pre-pass.

@@ -24,9 +24,15 @@ __device__ __forceinline__ void decode_block_pair(uint32_t t, uint32_t &r, uint3
     r = t - bb * (bb + 1) / 2;
 }
 
-// Dwords per profile row: LA rounded up to whole 16-byte reads, plus one
-// 16-byte pad so consecutive symbol rows start on different LDS banks.
-__host__ __device__ constexpr uint32_t profile_stride_dw_rt(int LA) { return (uint32_t)(((LA + 3) / 4) * 4 + 4); }
+// Dwords per profile row: LA rounded up to whole 16-byte reads, then to an
+// odd number of 16-byte units.  Lanes read the rows of different symbols at
+// the same offset in one ds_read_b128; with an odd row stride two rows share
+// an LDS bank group only when their symbols are congruent modulo the number
+// of bank groups, while an even stride makes many more rows collide.
+__host__ __device__ constexpr uint32_t profile_stride_dw_rt(int LA)
+{
+    return (uint32_t)((((LA + 3) / 4) | 1) * 4);
+}
 template <int LA>
 __host__ __device__ constexpr uint32_t profile_stride_dw()
 {
