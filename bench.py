@@ -82,6 +82,37 @@ def cpu_baseline(v, k, gpu_scores, gpu_index, budget_s):
     return rec, ok, done
 
 
+def serve(nw, dv, rates, nq, main_ms, cells):
+    """Served form: open-loop Poisson arrivals against the resident dictionary."""
+    import numpy as np
+    import synth
+    k = 16
+    srv = nw.Server(dv, k=k, max_batch=256, num_slots=4)
+    # warm the server's kernels
+    wq = synth.query_words(512, seed=49)
+    srv.replay(wq.symbols, wq.offsets, np.linspace(0, 0.01, wq.n))
+    out = []
+    total_l = int(dv.offsets[-1])
+    for t, rate in enumerate(rates):
+        q = synth.query_words(nq, seed=50 + t)
+        arr = synth.poisson_arrivals(rate, q.n, seed=150 + t)
+        b0, _ = srv.stats()
+        t0 = time.perf_counter()
+        sc, ix, lat = srv.replay(q.symbols, q.offsets, arr)
+        wall = time.perf_counter() - t0
+        b1, _ = srv.stats()
+        qcells = int(q.lengths.sum()) * total_l
+        out.append({"offered_qps": rate, "queries": q.n, "achieved_qps": round(q.n / wall, 1),
+                    "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                    "batches": b1 - b0, "gcups_while_serving": round(qcells / wall / 1e9, 1)})
+    srv.close()
+    return {"workload": "top-16 per query against the resident 600,000-word dictionary; queries drawn like the "
+                        "dictionary, open-loop Poisson arrivals; latency = completion - scheduled arrival",
+            "k": k, "max_batch": 256, "slots": 4, "rates": out,
+            "plain_main_pass_gcups": round(cells / (main_ms / 1e3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +121,9 @@ def main():
     ap.add_argument("--workload", choices=["paper", "mid"], default="paper")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-rates", default="10000,50000",
+                    help="offered query rates (q/s) for the served form; empty to skip")
+    ap.add_argument("--serve-queries", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -169,6 +203,9 @@ def main():
                            "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
                            "kernel": "k_topk_tiled (all-pairs main pass, every LA)",
                            "issue_frac": round(cells / (main_ms / 1e3) / PEAK_ISSUE_CELLS, 4)}
+        if args.serve_rates:
+            rec["served"] = serve(nw, dv, [float(r) for r in args.serve_rates.split(",")], args.serve_queries,
+                                  rec["phase_ms"]["main_pass"], cells)
         sc, ix, h = out
         hist = h.cpu().numpy()
         assert int(hist.sum()) == E, "histogram does not count every pair once"

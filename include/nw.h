@@ -157,6 +157,54 @@ int nw_query_workspace_bytes(const nw_vocab *v, uint64_t n_q, uint64_t q_symbols
 int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_offsets, uint64_t n_q, uint32_t k,
              int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes, void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Query server: continuous batching over a resident dictionary.
+ * A scheduler thread admits the oldest waiting queries (up to max_batch) into
+ * any free slot; each slot has its own stream, workspace region and pinned
+ * buffers, so batches overlap on the device and requests arriving meanwhile
+ * start as soon as a slot (and its memory) frees up.  A query's result is the
+ * one nw_query gives for it alone.
+ * ------------------------------------------------------------------------- */
+typedef struct nw_server nw_server;
+
+/* Device workspace bytes of a server (num_slots regions).  k 1..64,
+ * max_batch 1..4096, num_slots 1..16. */
+int nw_server_workspace_bytes(const nw_vocab *v, uint32_t k, uint32_t max_batch, uint32_t num_slots,
+                              uint64_t *bytes);
+
+/* Start a server.  d_ws (caller-owned, 256-byte aligned) must stay valid,
+ * like v, until nw_server_destroy returns.  The server creates its own
+ * streams, events and pinned host buffers. */
+int nw_server_create(const nw_vocab *v, uint32_t k, uint32_t max_batch, uint32_t num_slots, void *d_ws,
+                     uint64_t ws_bytes, nw_server **out);
+
+/* Queue one query word (len symbols, copied).  tag is returned with the
+ * result; t_arrival_ns (nw_clock_ns() time base, 0 = now) is the time the
+ * latency is measured from.  Thread-safe. */
+int nw_server_submit(nw_server *s, const uint8_t *h_symbols, uint32_t len, uint64_t tag, int64_t t_arrival_ns);
+
+/* Collect up to max_results finished queries, waiting up to timeout_us for
+ * the first: tags[r], scores[r*k ..], indices[r*k ..], latency_ns[r]
+ * (completion - arrival).  *n_out receives the count.  Any output array may
+ * be NULL. */
+int nw_server_poll(nw_server *s, uint32_t max_results, int32_t timeout_us, uint64_t *tags, int16_t *scores,
+                   int32_t *indices, int64_t *latency_ns, uint32_t *n_out);
+
+/* Open-loop replay: submit query q at arrival_s[q] seconds after the start
+ * (from a submitter thread), collect every result into scores[q*k ..],
+ * indices[q*k ..] and latency_s[q] (completion - scheduled arrival). */
+int nw_server_replay(nw_server *s, const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t n_q,
+                     const double *arrival_s, int16_t *scores, int32_t *indices, double *latency_s);
+
+/* Batches and queries completed so far. */
+int nw_server_stats(nw_server *s, uint64_t *batches, uint64_t *queries);
+
+/* Finish the queued and running batches and release the server. */
+void nw_server_destroy(nw_server *s);
+
+/* The server clock (steady, nanoseconds). */
+int64_t nw_clock_ns(void);
+
 #ifdef __cplusplus
 }
 #endif

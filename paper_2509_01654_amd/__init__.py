@@ -63,6 +63,16 @@ def load_library(path: str = LIB_PATH):
                                                ctypes.POINTER(ctypes.c_float)]),
         "nw_query": (ctypes.c_int, [P, P, P, u64, u32, P, P, P, u64, P]),
     }
+    sig.update({
+        "nw_server_workspace_bytes": (ctypes.c_int, [P, u32, u32, u32, ctypes.POINTER(u64)]),
+        "nw_server_create": (ctypes.c_int, [P, u32, u32, u32, P, u64, ctypes.POINTER(P)]),
+        "nw_server_submit": (ctypes.c_int, [P, P, u32, u64, ctypes.c_int64]),
+        "nw_server_poll": (ctypes.c_int, [P, u32, ctypes.c_int32, P, P, P, P, ctypes.POINTER(u32)]),
+        "nw_server_replay": (ctypes.c_int, [P, P, P, u64, P, P, P, P]),
+        "nw_server_stats": (ctypes.c_int, [P, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "nw_server_destroy": (None, [P]),
+        "nw_clock_ns": (ctypes.c_int64, []),
+    })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
@@ -217,3 +227,65 @@ class Vocab:
                              ctypes.c_void_p(sc.data_ptr()), ctypes.c_void_p(ix.data_ptr()),
                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
         return sc, ix
+
+
+class Server:
+    """Continuous-batching query server over a resident dictionary (nw_server_*)."""
+
+    def __init__(self, vocab: Vocab, k: int = 16, max_batch: int = 256, num_slots: int = 4):
+        import torch
+        lib = load_library()
+        self.vocab, self.k = vocab, k
+        nbytes = ctypes.c_uint64()
+        _check(lib.nw_server_workspace_bytes(vocab._h, k, max_batch, num_slots, ctypes.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=vocab.device)
+        torch.cuda.synchronize(vocab.device)
+        h = ctypes.c_void_p()
+        _check(lib.nw_server_create(vocab._h, k, max_batch, num_slots, ctypes.c_void_p(self.ws.data_ptr()),
+                                    nbytes.value, ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, symbols, tag: int, t_arrival_ns: int = 0):
+        sym = np.ascontiguousarray(np.asarray(symbols, dtype=np.uint8))
+        _check(_lib.nw_server_submit(self._h, sym.ctypes.data, sym.shape[0], tag, t_arrival_ns))
+
+    def poll(self, max_results: int = 1024, timeout_us: int = 1000):
+        tags = np.zeros(max_results, np.uint64)
+        sc = np.zeros((max_results, self.k), np.int16)
+        ix = np.zeros((max_results, self.k), np.int32)
+        lat = np.zeros(max_results, np.int64)
+        n = ctypes.c_uint32()
+        _check(_lib.nw_server_poll(self._h, max_results, timeout_us, tags.ctypes.data, sc.ctypes.data, ix.ctypes.data,
+                                   lat.ctypes.data, ctypes.byref(n)))
+        m = n.value
+        return tags[:m], sc[:m], ix[:m], lat[:m]
+
+    def replay(self, qsymbols, qoffsets, arrival_s):
+        """Open-loop replay; returns (scores [nq,k], index [nq,k], latency_s [nq])."""
+        qsymbols = np.ascontiguousarray(np.asarray(qsymbols, dtype=np.uint8))
+        qoffsets = np.ascontiguousarray(np.asarray(qoffsets, dtype=np.uint64))
+        arrival_s = np.ascontiguousarray(np.asarray(arrival_s, dtype=np.float64))
+        nq = qoffsets.shape[0] - 1
+        sc = np.zeros((nq, self.k), np.int16)
+        ix = np.zeros((nq, self.k), np.int32)
+        lat = np.zeros(nq, np.float64)
+        _check(_lib.nw_server_replay(self._h, qsymbols.ctypes.data, qoffsets.ctypes.data, nq, arrival_s.ctypes.data,
+                                     sc.ctypes.data, ix.ctypes.data, lat.ctypes.data))
+        return sc, ix, lat
+
+    def stats(self):
+        b, q = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.nw_server_stats(self._h, ctypes.byref(b), ctypes.byref(q)))
+        return b.value, q.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.nw_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def clock_ns() -> int:
+    return load_library().nw_clock_ns()

@@ -34,6 +34,7 @@ def _la_splits():
 def _units():
     units = [
         ("nw_api", os.path.join(CSRC, "nw_api.cpp"), []),
+        ("nw_server", os.path.join(CSRC, "nw_server.cpp"), []),
         ("k_launch", os.path.join(CSRC, "k_launch.hip"), []),
     ]
     for lo, hi in _la_splits():

@@ -12,36 +12,14 @@
 #include <vector>
 
 #include "../../include/nw.h"
-#include "nw_internal.h"
 #include "k_topk.h"
+#include "nw_host.h"
+#include "nw_internal.h"
 
 using namespace nw;
 
-struct nw_vocab {
-    DevVocab dev;
-    std::vector<uint32_t> h_gp_off;   // host copy of dev.gp_off
-    std::vector<uint8_t> h_csym;      // host copy of the caller-order padded words
-    std::vector<uint8_t> h_clen;
-    int32_t smin = 0, smax = 0;       // similarity extremes
-    // phase timing of the last top-k call (HIP events on the caller's stream)
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    float phase_ms[3] = {0, 0, 0};
-    ~nw_vocab()
-    {
-        for (auto &e : ev)
-            if (e) hipEventDestroy(e);
-    }
-    uint64_t n = 0;
-    uint32_t max_len = 0;
-    uint64_t num_pairs = 0;
-    uint64_t num_cells = 0;
-    int32_t lo = 0, hi = 0;      // score bounds
-    bool symmetric = true;
-    void *d_mem = nullptr;
-    uint64_t d_bytes = 0;
-};
-
-namespace {
+namespace nw {
+namespace host {
 
 thread_local std::string g_err = "no error";
 
@@ -133,9 +111,11 @@ uint16_t f16_bits_of_int(int v)
     return b;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace nw
 
-namespace {
+namespace nw {
+namespace host {
 
 // ---------------------------------------------------------------- top-k
 struct TopkWs {
@@ -184,10 +164,6 @@ TopkWs topk_ws(uint64_t n, uint32_t k)
 }
 
 // ---------------------------------------------------------------- queries
-struct QueryWs {
-    uint64_t sym, pairs, off, orig, partial, total;
-    int nsplit;
-};
 
 int query_splits(uint64_t n_q)
 {
@@ -216,13 +192,6 @@ QueryWs query_ws(uint64_t n_q, uint32_t k)
     return w;
 }
 
-// Host image of a row set: words sorted by length, paired by equal length.
-struct RowImage {
-    std::vector<uint8_t> sym;      // [m * kWordBytes]
-    std::vector<int32_t> pairs;    // [np * 2]
-    std::vector<uint32_t> off;     // [kMaxLen + 2]
-    std::vector<int32_t> orig;     // [m]
-};
 
 // words: (length, pointer to symbols, output row)
 RowImage make_rows(const std::vector<std::pair<int, std::pair<const uint8_t *, int32_t>>> &words)
@@ -255,6 +224,13 @@ RowImage make_rows(const std::vector<std::pair<int, std::pair<const uint8_t *, i
     return R;
 }
 
+long query_lo(const nw_vocab *v, uint32_t qmax)
+{
+    // scores of a query pair lie in [max(lq, ld) * min(smin, p, 0), min(lq, ld) * max(smax, 0)]
+    const long L = std::max<long>(qmax, v->max_len);
+    return std::min<long>(v->dev.lo, L * std::min({(long)v->smin, (long)v->dev.gap, 0L}));
+}
+
 ColSet full_colset(const DevVocab &D)
 {
     ColSet C;
@@ -265,7 +241,10 @@ ColSet full_colset(const DevVocab &D)
     return C;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace nw
+
+using namespace nw::host;
 
 extern "C" {
 
@@ -494,6 +473,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     v->hi = (int32_t)hi;
     v->symmetric = symmetric;
     v->d_mem = d_mem;
+    hipGetDevice(&v->device);
     v->d_bytes = d_bytes;
     *out = v;
     return ok();
@@ -739,9 +719,7 @@ int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_
         qmax = std::max<uint32_t>(qmax, (uint32_t)l);
         rows[i] = {(int)l, {h_q_symbols + h_q_offsets[i], (int32_t)i}};
     }
-    // scores of a query pair lie in [max(lq, ld) * min(smin, p, 0), min(lq, ld) * max(smax, 0)]
-    const long L = std::max<long>(qmax, v->max_len);
-    const long lo = std::min<long>(D.lo, L * std::min({(long)v->smin, (long)D.gap, 0L}));
+    const long lo = query_lo(v, qmax);
     if (lo < -32768) return fail(NW_ERANGE, "query scores may fall below int16");
     RowImage img = make_rows(rows);
     // one contiguous host image of the row set -> one copy; the image lives
