@@ -205,6 +205,52 @@ void nw_server_destroy(nw_server *s);
 /* The server clock (steady, nanoseconds). */
 int64_t nw_clock_ns(void);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: the triangles of many dictionaries (each with its own words;
+ * every dictionary symmetric) in one graph-captured sequence of persistent
+ * launches.  Work items (dictionary, block pair, row length, chunk of row
+ * pairs) are ordered heaviest first inside row-length classes; one persistent
+ * kernel per class drains its queue.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t class_width;     /* 1: one persistent kernel per row length; 8: classes of 8 lengths */
+    uint32_t wg_per_cu;       /* persistent workgroups per compute unit (>= 1) */
+    uint32_t pairs_per_item;  /* row pairs per work item (0 = all of a block and length) */
+    uint32_t use_graph;       /* 1: capture once into a hipGraph and replay; 0: launch eagerly */
+} nw_batch_options;
+
+typedef struct nw_batch nw_batch;
+
+/* Device workspace bytes of a batch plan. */
+int nw_batch_workspace_bytes(const nw_vocab *const *v, uint32_t nv, const nw_batch_options *opt, uint64_t *bytes);
+
+/* Plan the batch: dictionary v[i] writes its whole triangle (row-major, as
+ * nw_all_pairs_scores with [0, E_i)) to d_outs[i] (dtype dt).  The plan, the
+ * dictionaries, the outputs and d_ws must stay valid until nw_batch_destroy.
+ * Synchronous (uploads the plan; captures the graph).
+ * Errors: NW_EINVAL, NW_ERANGE (bounds do not fit dt), NW_ENOMEM. */
+int nw_batch_create(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, nw_dtype dt,
+                    const nw_batch_options *opt, void *d_ws, uint64_t ws_bytes, nw_batch **out);
+
+/* Enqueue one run of the batch on hip_stream (a graph launch when captured). */
+int nw_batch_run(nw_batch *b, void *hip_stream);
+
+/* Number of work items and of persistent launches per run. */
+int nw_batch_info(const nw_batch *b, uint64_t *items, uint32_t *launches);
+
+void nw_batch_destroy(nw_batch *b);
+
+/* Choose nw_batch_options for this batch by timing candidates on it
+ * (coordinate search over class width, workgroups per CU and pairs per item;
+ * the workspace must hold the largest candidate plan, see
+ * nw_batch_workspace_bytes with pairs_per_item = 16).  With cache_path, a
+ * result cached for the same device and workload signature is returned
+ * without timing, and new results are appended (one JSON object per line).
+ * Overwrites the outputs. */
+int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, nw_dtype dt, void *d_ws,
+                      uint64_t ws_bytes, void *hip_stream, const char *cache_path, nw_batch_options *best,
+                      float *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

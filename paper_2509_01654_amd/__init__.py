@@ -32,6 +32,11 @@ class _Scoring(ctypes.Structure):
                 ("gap", ctypes.c_int32), ("submat", ctypes.c_void_p)]
 
 
+class _BatchOptions(ctypes.Structure):
+    _fields_ = [("class_width", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
+                ("pairs_per_item", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
+
+
 def load_library(path: str = LIB_PATH):
     """Load libnw.so (after torch, so both use the one HIP runtime)."""
     global _lib
@@ -72,6 +77,14 @@ def load_library(path: str = LIB_PATH):
         "nw_server_stats": (ctypes.c_int, [P, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
         "nw_server_destroy": (None, [P]),
         "nw_clock_ns": (ctypes.c_int64, []),
+        "nw_batch_workspace_bytes": (ctypes.c_int, [P, u32, ctypes.POINTER(_BatchOptions), ctypes.POINTER(u64)]),
+        "nw_batch_create": (ctypes.c_int, [P, u32, P, ctypes.c_int, ctypes.POINTER(_BatchOptions), P, u64,
+                                           ctypes.POINTER(P)]),
+        "nw_batch_run": (ctypes.c_int, [P, P]),
+        "nw_batch_info": (ctypes.c_int, [P, ctypes.POINTER(u64), ctypes.POINTER(u32)]),
+        "nw_batch_destroy": (None, [P]),
+        "nw_batch_autotune": (ctypes.c_int, [P, u32, P, ctypes.c_int, P, u64, P, ctypes.c_char_p,
+                                             ctypes.POINTER(_BatchOptions), ctypes.POINTER(ctypes.c_float)]),
     })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -289,3 +302,60 @@ class Server:
 
 def clock_ns() -> int:
     return load_library().nw_clock_ns()
+
+
+class Batch:
+    """Triangles of several dictionaries in one graph-captured persistent sequence (nw_batch_*)."""
+
+    def __init__(self, vocabs, dtype=None, class_width=8, wg_per_cu=4, pairs_per_item=64, use_graph=True,
+                 outs=None, autotune=False, cache_path=None, stream=None):
+        import torch
+        lib = load_library()
+        dtype = dtype or torch.int16
+        self.vocabs = list(vocabs)
+        self.dtype = dtype
+        self.dt = {torch.int8: NW_I8, torch.int16: NW_I16}[dtype]
+        nv = len(self.vocabs)
+        self._vh = (ctypes.c_void_p * nv)(*[v._h.value for v in self.vocabs])
+        dev = self.vocabs[0].device
+        self.outs = outs or [torch.empty(max(1, v.num_pairs), dtype=dtype, device=dev) for v in self.vocabs]
+        self._oh = (ctypes.c_void_p * nv)(*[o.data_ptr() for o in self.outs])
+        # workspace for the largest plan any option could need (finest items)
+        probe = _BatchOptions(1, 1, 16, 1)
+        need = ctypes.c_uint64()
+        _check(lib.nw_batch_workspace_bytes(self._vh, nv, ctypes.byref(probe), ctypes.byref(need)))
+        self.ws = torch.empty(need.value, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize(dev)
+        opt = _BatchOptions(class_width, wg_per_cu, pairs_per_item, 1 if use_graph else 0)
+        self.tuned_ms = None
+        if autotune:
+            ms = ctypes.c_float()
+            cp = cache_path.encode() if cache_path else None
+            _check(lib.nw_batch_autotune(self._vh, nv, self._oh, self.dt, ctypes.c_void_p(self.ws.data_ptr()),
+                                         self.ws.numel(), _stream_handle(stream), cp, ctypes.byref(opt),
+                                         ctypes.byref(ms)))
+            opt.use_graph = 1 if use_graph else 0
+            self.tuned_ms = ms.value
+        self.options = dict(class_width=opt.class_width, wg_per_cu=opt.wg_per_cu,
+                            pairs_per_item=opt.pairs_per_item, use_graph=opt.use_graph)
+        h = ctypes.c_void_p()
+        _check(lib.nw_batch_create(self._vh, nv, self._oh, self.dt, ctypes.byref(opt),
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_lib.nw_batch_run(self._h, _stream_handle(stream)))
+        return self.outs
+
+    def info(self):
+        items, launches = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(_lib.nw_batch_info(self._h, ctypes.byref(items), ctypes.byref(launches)))
+        return items.value, launches.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.nw_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

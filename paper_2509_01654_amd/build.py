@@ -31,15 +31,25 @@ def _la_splits():
     return [(int(a), int(b)) for a, b in re.findall(r"X\((\d+), (\d+)\)", m.group(1))]
 
 
+def _class8():
+    text = open(os.path.join(CSRC, "nw_kernels.h"), encoding="utf-8").read()
+    m = re.search(r"#define NW_CLASS8 (.*)", text)
+    return [(int(a), int(b)) for a, b in re.findall(r"X\((\d+), (\d+)\)", m.group(1))]
+
+
 def _units():
     units = [
         ("nw_api", os.path.join(CSRC, "nw_api.cpp"), []),
         ("nw_server", os.path.join(CSRC, "nw_server.cpp"), []),
+        ("nw_batch", os.path.join(CSRC, "nw_batch.cpp"), []),
         ("k_launch", os.path.join(CSRC, "k_launch.hip"), []),
     ]
     for lo, hi in _la_splits():
         units.append((f"k_inst_{lo}_{hi}", os.path.join(CSRC, "k_inst.hip"),
                       [f"-DNW_LA_LO={lo}", f"-DNW_LA_HI={hi}"]))
+    for lo, hi in _class8():
+        units.append((f"k_batch_inst_{lo}_{hi}", os.path.join(CSRC, "k_batch_inst.hip"),
+                      [f"-DNW_CLASS_LO={lo}", f"-DNW_CLASS_HI={hi}"]))
     return units
 
 

@@ -4,6 +4,7 @@
 // nw_fill_<NW_LA_LO>.
 #include <utility>
 
+#include "k_batch.h"
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_tri_tiled.h"
@@ -20,6 +21,7 @@ static void fill(KernelTables &t, std::integer_sequence<int, Is...>)
     ((t.tri[LO + Is] = reinterpret_cast<const void *>(&k_tri_tiled<LO + Is>)), ...);
     ((t.query[LO + Is] = reinterpret_cast<const void *>(&k_query_tiled<LO + Is>)), ...);
     ((t.topk[LO + Is] = reinterpret_cast<const void *>(&k_topk_tiled<LO + Is>)), ...);
+    ((t.persist1[LO + Is] = reinterpret_cast<const void *>(&k_tri_persist<LO + Is, LO + Is>)), ...);
 }
 
 void NW_CAT(nw_fill_, NW_LA_LO)(KernelTables &t)

@@ -5,6 +5,7 @@
 // the row index, and one DP per thread with its scratch in shared memory (one
 // row of the score matrix instead of the whole matrix).
 #define NW_LAUNCH_TU 1
+#include "k_batch.h"
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_tri_tiled.h"
@@ -62,6 +63,9 @@ const KernelTables &kernel_tables()
     static bool init = [] {
 #define X(lo, hi) nw_fill_##lo(t);
         NW_LA_SPLITS
+#undef X
+#define X(lo, hi) nw_fill_class_##lo(t);
+        NW_CLASS8
 #undef X
         return true;
     }();
@@ -166,6 +170,12 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_reset_counters, dim3((n + 63) / 64), dim3(64), 0, stream, counters, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_select(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n, int k, int lo,

@@ -20,16 +20,14 @@
 
 namespace nw {
 
+// One tile: row pairs [pbeg, pend) of block r (all of length LA) against the
+// columns of block b, scores of pair indices in [idx_begin, idx_end) stored to
+// `out` (int8 or int16).  All threads of the workgroup must call it; it ends
+// with a barrier, so the caller may reuse the LDS afterwards.
 template <int LA>
-__global__ __launch_bounds__(kThreads) void k_tri_tiled(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
-                                                        int out_kind)
+__device__ __forceinline__ void tri_tile(const DevVocab &V, uint32_t r, uint32_t b, uint32_t pbeg, uint32_t pend,
+                                         uint64_t idx_begin, uint64_t idx_end, void *out, int out_kind, uint8_t *lds)
 {
-    extern __shared__ __align__(16) uint8_t lds[];
-
-    uint32_t r, b;
-    decode_block_pair(blockIdx.x, r, b);
-    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
-    const uint32_t pbeg = rpo[0], pend = rpo[1];
     if (pbeg >= pend) return;
 
     const int64_t n = V.n, CB = V.CB;
@@ -42,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_tri_tiled(DevVocab V, uint64_t idx
         const uint64_t first = row_start_idx(n, I0) + (uint64_t)(jlo - I0 - 1);
         const int64_t ilast = (r == b) ? J1 - 2 : I1 - 1;
         const uint64_t last = row_start_idx(n, ilast) + (uint64_t)(J1 - 1 - ilast - 1);
-        if (last < idx_begin || first >= idx_end) return;
+        if (last < idx_begin || first >= idx_end) return;   // uniform: the whole workgroup skips
     }
 
     const int tid = threadIdx.x;
@@ -101,6 +99,18 @@ __global__ __launch_bounds__(kThreads) void k_tri_tiled(DevVocab V, uint64_t idx
             }
         }
     }
+}
+
+
+template <int LA>
+__global__ __launch_bounds__(kThreads) void k_tri_tiled(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
+                                                        int out_kind)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t r, b;
+    decode_block_pair(blockIdx.x, r, b);
+    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
+    tri_tile<LA>(V, r, b, rpo[0], rpo[1], idx_begin, idx_end, out, out_kind, lds);
 }
 
 }  // namespace nw

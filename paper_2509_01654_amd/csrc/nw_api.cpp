@@ -463,6 +463,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     v->h_gp_off = h_gp_off;
     v->h_csym.assign(csym, csym + n * L.WB);
     v->h_clen.assign(clen, clen + n);
+    v->h_rp_off.assign(rp_off, rp_off + (size_t)L.nb * (LM + 1) + 1);
     v->smin = smin;
     v->smax = smax;
     v->n = n;
