@@ -64,7 +64,10 @@ typedef struct nw_vocab nw_vocab;
 /* Thread-local text of the last error (never NULL). */
 const char *nw_last_error(void);
 
-/* Longest word (symbols) the kernels accept. */
+/* Longest word (symbols) the triangle calls accept (255).  The register-row
+ * kernels behind top-k, queries, the batched form and the server take words
+ * of at most 48 symbols; a dictionary with longer words is scored by the
+ * anti-diagonal kernel and is refused (NW_EINVAL) by those calls. */
 int nw_max_word_length(void);
 
 /* Device bytes nw_load_vocab needs for n words holding total_symbols symbols,
@@ -108,6 +111,14 @@ int nw_score_bounds(const nw_vocab *v, int32_t *lo, int32_t *hi);
  * NW_ERANGE (the score bounds do not fit dt). */
 int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
                         void *d_out, void *hip_stream);
+
+/* The same scores computed by the intra-pair anti-diagonal kernel: 16 lanes
+ * per pair walk the score matrix by anti-diagonals (the stencil
+ * parallelisation the paper proposes in Section 6).  nw_all_pairs_scores uses
+ * it by itself for words longer than 48; this entry point forces it (for
+ * comparison with the register-row kernel).  Same arguments and errors. */
+int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
+                             void *d_out, void *hip_stream);
 
 /* The same scores computed by the one-thread-per-pair scheme of Section 4.2
  * (1-D grid, idx -> (row, column), one DP per thread).  Kept as the plain

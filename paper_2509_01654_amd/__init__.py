@@ -61,6 +61,7 @@ def load_library(path: str = LIB_PATH):
         "nw_score_bounds": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "nw_all_pairs_scores": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
         "nw_all_pairs_scores_naive": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
+        "nw_all_pairs_scores_diag": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
         "nw_topk_workspace_bytes": (ctypes.c_int, [P, u32, ctypes.POINTER(u64)]),
         "nw_all_pairs_topk": (ctypes.c_int, [P, u32, P, P, P, P, u64, P]),
         "nw_query_workspace_bytes": (ctypes.c_int, [P, u64, u64, u32, ctypes.POINTER(u64)]),
@@ -183,6 +184,12 @@ class Vocab:
         """Same output through the one-thread-per-pair kernel."""
         import torch
         return self._triangle(_lib.nw_all_pairs_scores_naive, idx_begin, idx_end, dtype or torch.int8, out, stream)
+
+    def all_pairs_scores_diag(self, idx_begin: int = 0, idx_end: int | None = None, dtype=None, out=None,
+                              stream=None):
+        """Same output through the intra-pair anti-diagonal kernel."""
+        import torch
+        return self._triangle(_lib.nw_all_pairs_scores_diag, idx_begin, idx_end, dtype or torch.int8, out, stream)
 
     # ------------------------------------------------------------------ top-k
     def topk_workspace_bytes(self, k: int) -> int:

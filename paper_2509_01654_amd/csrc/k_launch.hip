@@ -6,6 +6,7 @@
 // row of the score matrix instead of the whole matrix).
 #define NW_LAUNCH_TU 1
 #include "k_batch.h"
+#include "k_diag.h"
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_tri_tiled.h"
@@ -13,16 +14,17 @@
 
 namespace nw {
 
-template <typename OutT>
-__global__ __launch_bounds__(256) void k_tri_naive(DevVocab V, uint64_t idx_begin, uint64_t idx_end, OutT *out)
+// CAP: scratch row capacity (longest word + 1); NT: threads per block.
+template <typename OutT, int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_tri_naive(DevVocab V, uint64_t idx_begin, uint64_t idx_end, OutT *out)
 {
-    __shared__ int16_t rows[256][kMaxLen + 1];
+    __shared__ int16_t rows[NT][CAP];
     int16_t *row = rows[threadIdx.x];   // this thread's scratch: one row of the score matrix
     const int64_t n = V.n;
     const int gap = V.gap;
     const double z = (double)n - 0.5;
-    for (uint64_t idx = idx_begin + (uint64_t)blockIdx.x * 256u + threadIdx.x; idx < idx_end;
-         idx += (uint64_t)gridDim.x * 256u) {
+    for (uint64_t idx = idx_begin + (uint64_t)blockIdx.x * NT + threadIdx.x; idx < idx_end;
+         idx += (uint64_t)gridDim.x * NT) {
         // r = floor(z - sqrt(z^2 - 2 idx)), z = n - 1/2 (Section 4.2), then an
         // integer fix-up so rounding can never pick the wrong row
         int64_t r = (int64_t)floor(z - sqrt(z * z - 2.0 * (double)idx));
@@ -105,15 +107,54 @@ hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t
 {
     if (idx_begin >= idx_end) return hipSuccess;
     const uint64_t count = idx_end - idx_begin;
-    const uint64_t blocks = (count + 255) / 256;
+    const bool lng = V.lmax > kMaxLen;
+    const uint64_t nt = lng ? 64 : 256;
+    const uint64_t blocks = (count + nt - 1) / nt;
     const uint32_t grid = (uint32_t)(blocks < (1u << 20) ? blocks : (1u << 20));
-    if (out_kind == OUT_I8)
-        hipLaunchKernelGGL(k_tri_naive<int8_t>, dim3(grid), dim3(256), 0, stream, V, idx_begin, idx_end,
-                           (int8_t *)d_out);
+    if (!lng && out_kind == OUT_I8)
+        hipLaunchKernelGGL((k_tri_naive<int8_t, kMaxLen + 1, 256>), dim3(grid), dim3(256), 0, stream, V, idx_begin,
+                           idx_end, (int8_t *)d_out);
+    else if (!lng)
+        hipLaunchKernelGGL((k_tri_naive<int16_t, kMaxLen + 1, 256>), dim3(grid), dim3(256), 0, stream, V, idx_begin,
+                           idx_end, (int16_t *)d_out);
+    else if (out_kind == OUT_I8)
+        hipLaunchKernelGGL((k_tri_naive<int8_t, kLongMaxLen + 1, 64>), dim3(grid), dim3(64), 0, stream, V, idx_begin,
+                           idx_end, (int8_t *)d_out);
     else
-        hipLaunchKernelGGL(k_tri_naive<int16_t>, dim3(grid), dim3(256), 0, stream, V, idx_begin, idx_end,
-                           (int16_t *)d_out);
+        hipLaunchKernelGGL((k_tri_naive<int16_t, kLongMaxLen + 1, 64>), dim3(grid), dim3(64), 0, stream, V, idx_begin,
+                           idx_end, (int16_t *)d_out);
     return hipGetLastError();
+}
+
+hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
+                                hipStream_t stream)
+{
+    if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
+    const uint32_t nblk_pairs = (uint32_t)((uint64_t)V.nb * (V.nb + 1) / 2);
+    const KernelTables &tab = kernel_tables();
+    for (int LA = 0; LA <= V.lmax; ++LA) {
+        DevVocab Vc = V;
+        uint64_t ib = idx_begin, ie = idx_end;
+        void *po = d_out;
+        int ok = out_kind;
+        hipError_t e;
+        if (LA == 0) {
+            void *args[] = {&Vc, &ib, &ie, &po, &ok};
+            e = launch_dyn(tab.tri[0], dim3(nblk_pairs), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
+        } else {
+            // rows per lane: the smallest class whose 16 lanes cover LA rows
+            const int R = LA <= 64 ? 4 : LA <= 128 ? 8 : LA <= 192 ? 12 : 16;
+            const void *fn = R == 4 ? reinterpret_cast<const void *>(&k_tri_diag<4>)
+                           : R == 8 ? reinterpret_cast<const void *>(&k_tri_diag<8>)
+                           : R == 12 ? reinterpret_cast<const void *>(&k_tri_diag<12>)
+                                     : reinterpret_cast<const void *>(&k_tri_diag<16>);
+            int la = LA;
+            void *args[] = {&Vc, &ib, &ie, &po, &ok, &la};
+            e = launch_dyn(fn, dim3(nblk_pairs), diag_lds_bytes(R, V.alphabet, V.CB), stream, args);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_off, const ColSet &C, int k,

@@ -72,7 +72,7 @@ Layout make_layout(uint64_t n, uint32_t max_len)
     Layout L{};
     L.CB = choose_block(n);
     (void)max_len;
-    L.WB = kWordBytes;
+    L.WB = max_len <= (uint32_t)kMaxLen ? kWordBytes : 256;   // whole 16-byte units
     L.nb = (int)((n + L.CB - 1) / L.CB);
     const uint64_t slots = (uint64_t)L.nb * L.CB;
     uint64_t o = 0;
@@ -87,7 +87,7 @@ Layout make_layout(uint64_t n, uint32_t max_len)
     L.blen = take(slots);
     L.bcol = take(slots * 2);
     L.rpairs = take(slots * 2 * 4);
-    L.rp_off = take(((uint64_t)L.nb * (kMaxLen + 1) + 1) * 4);
+    L.rp_off = take(((uint64_t)L.nb * (std::max<uint32_t>(max_len, 1) + 1) + 1) * 4);
     L.wtab = take(256 * 256 * 2);
     L.submat = take(256 * 256);
     L.borig = take(slots * 4);
@@ -250,13 +250,13 @@ extern "C" {
 
 const char *nw_last_error(void) { return g_err.c_str(); }
 
-int nw_max_word_length(void) { return kMaxLen; }
+int nw_max_word_length(void) { return kLongMaxLen; }
 
 int nw_vocab_bytes(uint64_t n, uint64_t total_symbols, uint32_t max_len, uint64_t *dev_bytes)
 {
     (void)total_symbols;
     if (!dev_bytes) return fail(NW_EINVAL, "dev_bytes is NULL");
-    if (max_len > (uint32_t)kMaxLen) return fail(NW_EINVAL, "max_len %u exceeds the maximum word length %d", max_len, kMaxLen);
+    if (max_len > (uint32_t)kLongMaxLen) return fail(NW_EINVAL, "max_len %u exceeds the maximum word length %d", max_len, kLongMaxLen);
     if (n >= (1ull << 31)) return fail(NW_EINVAL, "n must be < 2^31");
     *dev_bytes = make_layout(n, max_len).total;
     return ok();
@@ -282,9 +282,9 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     for (uint64_t i = 0; i < n; ++i) {
         if (h_offsets[i + 1] < h_offsets[i]) return fail(NW_EINVAL, "offsets decrease at word %llu", (unsigned long long)i);
         const uint64_t l = h_offsets[i + 1] - h_offsets[i];
-        if (l > (uint64_t)kMaxLen)
+        if (l > (uint64_t)kLongMaxLen)
             return fail(NW_EINVAL, "word %llu has %llu symbols; the maximum is %d", (unsigned long long)i,
-                        (unsigned long long)l, kMaxLen);
+                        (unsigned long long)l, kLongMaxLen);
         max_len = std::max<uint32_t>(max_len, (uint32_t)l);
         sum_l += l;
         sum_l2 += l * l;
@@ -519,9 +519,24 @@ int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end,
 {
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
     if (rc) return rc;
-    hipError_t e = launch_triangle_tiled(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
-                                         (hipStream_t)hip_stream);
-    if (e != hipSuccess) return dev_fail(e, "launching the tiled triangle kernel");
+    // words longer than the register-row limit take the anti-diagonal kernel
+    hipError_t e = v->max_len > (uint32_t)kMaxLen
+                       ? launch_triangle_diag(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
+                                              (hipStream_t)hip_stream)
+                       : launch_triangle_tiled(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
+                                               (hipStream_t)hip_stream);
+    if (e != hipSuccess) return dev_fail(e, "launching the triangle kernels");
+    return ok();
+}
+
+int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, void *d_out,
+                             void *hip_stream)
+{
+    int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
+    if (rc) return rc;
+    hipError_t e = launch_triangle_diag(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
+                                        (hipStream_t)hip_stream);
+    if (e != hipSuccess) return dev_fail(e, "launching the anti-diagonal triangle kernel");
     return ok();
 }
 
@@ -551,6 +566,8 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     if (!v) return fail(NW_EINVAL, "vocab is NULL");
     if (k < 1 || k > 63) return fail(NW_EINVAL, "k = %u outside 1..63", k);
     if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
+    if (v->max_len > (uint32_t)kMaxLen)
+        return fail(NW_EINVAL, "top-k supports words of at most %d symbols (this dictionary has %u)", kMaxLen, v->max_len);
     const uint64_t n = v->n;
     const TopkWs W = topk_ws(n, k);
     if (n > 0 && (!d_score || !d_index)) return fail(NW_EINVAL, "d_score / d_index is NULL");
@@ -701,6 +718,8 @@ int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_
     if (n_q == 0) return ok();
     if (!h_q_offsets || !d_score || !d_index) return fail(NW_EINVAL, "NULL argument");
     if (n_q >= (1ull << 31)) return fail(NW_EINVAL, "n_q must be < 2^31");
+    if (v->max_len > (uint32_t)kMaxLen)
+        return fail(NW_EINVAL, "queries support dictionaries of words of at most %d symbols", kMaxLen);
     const QueryWs W = query_ws(n_q, k);
     if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
     if (ws_bytes < W.total)

@@ -174,6 +174,7 @@ int nw_batch_create(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, 
     for (uint32_t i = 0; i < nv; ++i) {
         if (!v[i]) return fail(NW_EINVAL, "dictionary %u is NULL", i);
         if (!v[i]->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
+        if (v[i]->max_len > (uint32_t)kMaxLen) return fail(NW_EINVAL, "batched form supports words of at most %d symbols", kMaxLen);
         if (dt == NW_I8 && (v[i]->lo < -128 || v[i]->hi > 127))
             return fail(NW_ERANGE, "score bounds of dictionary %u do not fit int8", i);
         if (v[i]->num_pairs && !d_outs[i]) return fail(NW_EINVAL, "output %u is NULL", i);

@@ -9,9 +9,11 @@
 
 namespace nw {
 
-// Longest word the kernels accept (the register-resident DP column of the
-// tiled kernel is unrolled per exact length up to this bound).
+// Longest word of the register-row kernels (the DP column is unrolled per
+// exact length up to this bound); the anti-diagonal kernel takes longer words
+// (up to kLongMaxLen) for the triangle calls.
 constexpr int kMaxLen = 48;
+constexpr int kLongMaxLen = 255;   // lengths are stored as uint8
 // Threads per workgroup of the tiled kernels (four wave64 wavefronts).
 constexpr int kThreads = 256;
 // Bytes of a padded word in the blocked layout (kMaxLen symbols, whole 16-byte loads).
@@ -76,6 +78,9 @@ hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t
                                  void *d_out, hipStream_t stream);
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
                                  void *d_out, hipStream_t stream);
+// Anti-diagonal (16 lanes per pair) kernel, words up to 256 symbols.
+hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
+                                void *d_out, hipStream_t stream);
 
 // Per-row top-k lists of the rows R (pairs grouped by length, h_off = host
 // copy of R.off) against the column set C, split over nsplit column ranges:

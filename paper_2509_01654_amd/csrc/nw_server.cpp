@@ -230,6 +230,7 @@ int nw_server_create(const nw_vocab *v, uint32_t k, uint32_t max_batch, uint32_t
     uint64_t need = 0;
     int rc = nw_server_workspace_bytes(v, k, max_batch, num_slots, &need);
     if (rc) return rc;
+    if (v->max_len > (uint32_t)kMaxLen) return fail(NW_EINVAL, "the server supports words of at most %d symbols", kMaxLen);
     if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
     if (ws_bytes < need)
         return fail(NW_ENOMEM, "workspace holds %llu bytes; the server needs %llu", (unsigned long long)ws_bytes,

@@ -30,13 +30,14 @@ def test_exports_every_declared_symbol():
 
 
 def test_vocab_bytes_and_limits():
-    assert nw.max_word_length() == 48
+    assert nw.max_word_length() == 255
     assert nw.vocab_bytes(0, 0, 0) > 0
     b1 = nw.vocab_bytes(2000, 14000, 20)
     b2 = nw.vocab_bytes(50000, 350000, 20)
     assert b2 > b1
+    assert nw.vocab_bytes(2000, 14000, 200) > b1
     with pytest.raises(nw.NwError) as e:
-        nw.vocab_bytes(10, 10, 49)
+        nw.vocab_bytes(10, 10, 256)
     assert e.value.code == nw.NW_EINVAL
 
 
@@ -57,8 +58,8 @@ def test_load_vocab_rejects_bad_input_before_any_device_call():
     pm = nw.Scoring(40, 1, -1, -1)
     rc, msg = _load(np.array([1, 40], np.uint8), np.array([0, 2], np.uint64), pm)
     assert rc == nw.NW_EINVAL and "alphabet" in msg
-    long_word = np.zeros(49, np.uint8)
-    rc, msg = _load(long_word, np.array([0, 49], np.uint64), pm)
+    long_word = np.zeros(256, np.uint8)
+    rc, msg = _load(long_word, np.array([0, 256], np.uint64), pm)
     assert rc == nw.NW_EINVAL and "maximum" in msg
     rc, _ = _load(ok_syms, ok_offs, nw.Scoring(40, 1, -1, +1))
     assert rc == nw.NW_EINVAL
