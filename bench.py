@@ -170,17 +170,55 @@ def bench_batched(args, nw, synth, torch, dev):
     }
 
 
+def _time(fn, torch, steps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_diag(args, nw, synth, torch, dev):
+    """Anti-diagonal kernel against the register-row kernel on the longest
+    batched vocabulary (100,000 words, lengths 1..48), and alone on words of
+    up to 255 symbols."""
+    vocabs, S = synth.batched_configs()
+    sc = nw.Scoring(64, submat=S, gap=-2)
+    v = vocabs[-1]
+    dv = nw.Vocab(v.symbols, v.offsets, sc, device=dev)
+    out = torch.empty(dv.num_pairs, dtype=torch.int16, device=dev)
+    t_row = _time(lambda: dv.all_pairs_scores(dtype=torch.int16, out=out), torch, args.steps)
+    t_diag = _time(lambda: dv.all_pairs_scores_diag(dtype=torch.int16, out=out), torch, args.steps)
+    lv = synth.uniform_vocab(20000, seed=90, alphabet=64, min_len=1, max_len=255)
+    dl = nw.Vocab(lv.symbols, lv.offsets, sc, device=dev)
+    out2 = torch.empty(dl.num_pairs, dtype=torch.int16, device=dev)
+    t_long = _time(lambda: dl.all_pairs_scores(dtype=torch.int16, out=out2), torch, args.steps)
+    return {"workload": "anti-diagonal vs register-row kernel", "steps": args.steps,
+            "short_words": {"words": dv.n, "lengths": "1..48", "cells": dv.num_cells,
+                            "register_row_ms": round(t_row, 3), "anti_diagonal_ms": round(t_diag, 3),
+                            "register_row_gcups": round(dv.num_cells / t_row / 1e6, 1),
+                            "anti_diagonal_gcups": round(dv.num_cells / t_diag / 1e6, 1)},
+            "long_words": {"words": dl.n, "lengths": "1..255", "cells": dl.num_cells, "ms": round(t_long, 3),
+                           "gcups": round(dl.num_cells / t_long / 1e6, 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["paper", "mid", "batched"], default="paper")
+    ap.add_argument("--workload", choices=["paper", "mid", "batched", "diag"], default="paper")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-rates", default="10000,50000",
                     help="offered query rates (q/s) for the served form; empty to skip")
     ap.add_argument("--serve-queries", type=int, default=20000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -195,8 +233,20 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": 1 << 30,
+                          "bytes_written_per_copy": 1 << 30, "copies": 4}), flush=True)
+        return
     if args.workload == "batched":
         print(json.dumps(bench_batched(args, nw, synth, torch, dev)), flush=True)
+        return
+    if args.workload == "diag":
+        print(json.dumps(bench_diag(args, nw, synth, torch, dev)), flush=True)
         return
     v = synth.plain_config(args.workload)
     dv = nw.Vocab(v.symbols, v.offsets, nw.Scoring(40, 1, -1, -1), device=dev)

@@ -219,6 +219,14 @@ hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t stream)
     return hipGetLastError();
 }
 
+hipError_t launch_tighten(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n, int k, uint64_t *thr,
+                          hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tighten, dim3((uint32_t)((n + 3) / 4)), dim3(256), 0, stream, cnt, lists, cap, n, k, thr);
+    return hipGetLastError();
+}
+
 hipError_t launch_select(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n, int k, int lo,
                          int16_t *score, int32_t *index, uint32_t *ovf_count, int32_t *ovf_list, hipStream_t stream)
 {

@@ -20,20 +20,27 @@
 namespace nw {
 
 struct TopkArgs {
-    const uint64_t *thr;        // [n] threshold keys
+    uint64_t *thr;              // [n] threshold keys
     uint32_t *cnt;              // [n] candidate counters (zeroed)
     uint64_t *lists;            // [n][cap]
     uint32_t cap;
     unsigned long long *hist;   // [nbins] or NULL
     int lo;                     // lowest score (key and bin origin)
     int nbins;
+    // block pairs of this launch: (b - r) mod phase_mod in [phase_lo, phase_hi]
+    int phase_mod, phase_lo, phase_hi;
 };
 
-constexpr int kLdsHistMax = 4096;
+// The LDS histogram is kept in kHistCopies copies (copy = lane mod
+// kHistCopies) so that lanes adding to the same popular bin in one
+// instruction mostly hit different addresses; the copies are summed at the end.
+constexpr int kHistCopies = 16;
+constexpr int kLdsHistMax = 1024;
 
+__host__ __device__ constexpr uint32_t hist_stride(int nbins) { return (uint32_t)(nbins | 1); }
 __host__ __device__ constexpr uint32_t topk_lds_bytes(int LA, int alphabet, int nbins)
 {
-    return 2u * profile_bytes(LA, alphabet) + 4u * (uint32_t)(nbins <= kLdsHistMax ? nbins : 0);
+    return 2u * profile_bytes(LA, alphabet) + (nbins <= kLdsHistMax ? 4u * kHistCopies * hist_stride(nbins) : 0u);
 }
 
 __device__ __forceinline__ void emit_candidate(const TopkArgs &T, int64_t w, uint64_t key)
@@ -48,6 +55,8 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t r, b;
     decode_block_pair(blockIdx.x, r, b);
+    const int ph = (int)((b - r) % (uint32_t)T.phase_mod);
+    if (ph < T.phase_lo || ph > T.phase_hi) return;
     const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
     const uint32_t pbeg = rpo[0], pend = rpo[1];
     if (pbeg >= pend) return;
@@ -59,9 +68,11 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
     const int wave = tid >> 6, lane = tid & 63;
     const uint32_t prof_bytes = profile_bytes(LA, V.alphabet);
     const bool lds_hist = T.hist != nullptr && T.nbins <= kLdsHistMax;
-    uint32_t *hist = reinterpret_cast<uint32_t *>(lds + 2 * prof_bytes);
+    const uint32_t hs = hist_stride(T.nbins);
+    uint32_t *hist_all = reinterpret_cast<uint32_t *>(lds + 2 * prof_bytes);
+    uint32_t *hist = hist_all + (lane & (kHistCopies - 1)) * hs;   // this lane's copy
     if (lds_hist)
-        for (int i = tid; i < T.nbins; i += kThreads) hist[i] = 0;
+        for (int i = tid; i < kHistCopies * (int)hs; i += kThreads) hist_all[i] = 0;
     const ProfileRole role = profile_role(tid, V.alphabet);
     const int CPL = V.CB / kThreads;
 
@@ -120,12 +131,38 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
     }
     if (lds_hist) {
         __syncthreads();
-        for (int i = tid; i < T.nbins; i += kThreads)
-            if (hist[i]) atomicAdd(&T.hist[i], (unsigned long long)hist[i]);
+        for (int i = tid; i < T.nbins; i += kThreads) {
+            uint32_t sum = 0;
+            for (int c = 0; c < kHistCopies; ++c) sum += hist_all[c * hs + i];
+            if (sum) atomicAdd(&T.hist[i], (unsigned long long)sum);
+        }
     }
 }
 
 #ifdef NW_LAUNCH_TU   // non-template kernels: compiled in the launcher unit only
+// One wavefront per word: raise thr[w] to the k-th best key among the
+// candidates collected so far (real keys of real partners, so it stays a
+// lower bound of the final k-th key).
+__global__ __launch_bounds__(256) void k_tighten(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n,
+                                                 int k, uint64_t *thr)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n) return;
+    const uint32_t c = cnt[w];
+    const int m = (int)(c < cap ? c : cap);
+    if (m < k) return;
+    const uint64_t *src = lists + w * (int64_t)cap;
+    uint64_t list = 0, t = 0;
+    for (int base = 0; base < m; base += 64) {
+        const int i = base + lane;
+        const uint64_t key = i < m ? src[i] : 0;
+        wl_offer(list, t, key, k, lane);
+    }
+    const uint64_t kth = readlane64(list, k - 1);
+    if (lane == 0 && kth > thr[w]) thr[w] = kth;
+}
+
 // One wavefront per word: the best k of its (at most cap) candidates.
 // Words with more than cap candidates are appended to ovf_list.
 __global__ __launch_bounds__(256) void k_select(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n,

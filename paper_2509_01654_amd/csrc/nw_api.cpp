@@ -610,7 +610,11 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     if ((e = launch_merge(partial, 4, (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
         return dev_fail(e, "launching the threshold merge");
     if ((e = hipEventRecord(vm->ev[1], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
-    // 2. every unordered pair once: candidates for both endpoints, histogram
+    // 2. every unordered pair once: candidates for both endpoints, histogram.
+    // Two phases: block pairs with (b - r) mod 8 == 0 first -- every word meets
+    // an eighth of its partners, spread over the whole dictionary -- then each
+    // word's threshold is raised to the k-th best of its candidates so far,
+    // and the remaining block pairs emit far fewer candidates.
     TopkArgs T;
     T.thr = thr;
     T.cnt = cnt;
@@ -619,6 +623,14 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     T.hist = reinterpret_cast<unsigned long long *>(d_hist);
     T.lo = D.lo;
     T.nbins = nbins;
+    T.phase_mod = 8;
+    T.phase_lo = 0;
+    T.phase_hi = 0;
+    if ((e = launch_topk_main(D, T, st)) != hipSuccess) return dev_fail(e, "launching the top-k main pass");
+    if ((e = launch_tighten(cnt, lists, W.cap, (int64_t)n, (int)k, thr, st)) != hipSuccess)
+        return dev_fail(e, "launching the threshold update");
+    T.phase_lo = 1;
+    T.phase_hi = 7;
     if ((e = launch_topk_main(D, T, st)) != hipSuccess) return dev_fail(e, "launching the top-k main pass");
     if ((e = hipEventRecord(vm->ev[2], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 3. the best k of each word's candidates

@@ -101,6 +101,10 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
 // Zero n counters (a kernel, so graph capture records no memset node).
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t stream);
 
+// Raise each word's threshold to the k-th best of its candidates so far.
+hipError_t launch_tighten(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n, int k, uint64_t *thr,
+                          hipStream_t stream);
+
 // Final per-word selection from the candidate lists.
 hipError_t launch_select(const uint32_t *cnt, const uint64_t *lists, uint32_t cap, int64_t n, int k, int lo,
                          int16_t *score, int32_t *index, uint32_t *ovf_count, int32_t *ovf_list, hipStream_t stream);
