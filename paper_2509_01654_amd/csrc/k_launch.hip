@@ -206,8 +206,8 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
         DevVocab Vc = V;
         TopkArgs Tc = T;
         void *args[] = {&Vc, &Tc};
-        hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs), topk_lds_bytes(LA, V.alphabet, T.nbins), stream,
-                                  args);
+        hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs), topk_lds_bytes(LA, V.alphabet, T.nbins, V.CB),
+                                  stream, args);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -38,9 +38,15 @@ constexpr int kHistCopies = 16;
 constexpr int kLdsHistMax = 1024;
 
 __host__ __device__ constexpr uint32_t hist_stride(int nbins) { return (uint32_t)(nbins | 1); }
-__host__ __device__ constexpr uint32_t topk_lds_bytes(int LA, int alphabet, int nbins)
+__host__ __device__ constexpr uint32_t topk_hist_bytes(int nbins)
 {
-    return 2u * profile_bytes(LA, alphabet) + (nbins <= kLdsHistMax ? 4u * kHistCopies * hist_stride(nbins) : 0u);
+    return nbins <= kLdsHistMax ? 4u * kHistCopies * hist_stride(nbins) : 0u;
+}
+// LDS: two profile buffers, the histogram copies, and the column block's
+// per-slot metadata (length, column, threshold score; 8 bytes per slot).
+__host__ __device__ constexpr uint32_t topk_lds_bytes(int LA, int alphabet, int nbins, int CB)
+{
+    return 2u * profile_bytes(LA, alphabet) + topk_hist_bytes(nbins) + 8u * (uint32_t)CB;
 }
 
 __device__ __forceinline__ void emit_candidate(const TopkArgs &T, int64_t w, uint64_t key)
@@ -73,8 +79,20 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
     uint32_t *hist = hist_all + (lane & (kHistCopies - 1)) * hs;   // this lane's copy
     if (lds_hist)
         for (int i = tid; i < kHistCopies * (int)hs; i += kThreads) hist_all[i] = 0;
+    // The column block's slots are the same for every row pair: stage their
+    // metadata once -- x = column | length << 16, y = score of the column
+    // word's threshold (a pair can only enter that word's list at or above it)
+    uint2 *meta = reinterpret_cast<uint2 *>(lds + 2 * prof_bytes + topk_hist_bytes(T.nbins));
+    for (int i = tid; i < CB; i += kThreads) {
+        const int64_t slot = J0 + i;
+        const uint32_t col = V.bcol[slot];
+        const uint32_t lb = V.blen[slot];
+        const int ts = col != 0xFFFF ? key_score(T.thr[J0 + col], T.lo) : 0x7FFFFFFF;
+        meta[i] = make_uint2(col | (lb << 16), (uint32_t)ts);
+    }
     const ProfileRole role = profile_role(tid, V.alphabet);
     const int CPL = V.CB / kThreads;
+    const int lane_base = wave * 64 * CPL + lane;   // this lane's first slot in the block
 
     for (uint32_t k = pbeg; k < pend; ++k) {
         const int32_t a0 = V.rpairs[2 * k], a1 = V.rpairs[2 * k + 1];
@@ -89,17 +107,23 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
         // a key >= thr needs score >= the threshold's score: test that first
         const int ts_u0 = key_score(thr_u0, T.lo);
         const int ts_u1 = key_score(thr_u1, T.lo);
+        // the next lane word's symbols are fetched while this one runs
+        uint32_t bw_next[kWordBytes / 4];
+        load_word(bw_next, V.bsym + (J0 + lane_base) * kWordBytes);
         for (int c = 0; c < CPL; ++c) {
-            const int64_t slot = J0 + (int64_t)(wave * 64 * CPL + c * 64 + lane);
-            const int lb = V.blen[slot];
+            uint32_t bw[kWordBytes / 4];
+#pragma unroll
+            for (int q = 0; q < kWordBytes / 4; ++q) bw[q] = bw_next[q];
+            if (c + 1 < CPL) load_word(bw_next, V.bsym + (J0 + lane_base + (c + 1) * 64) * kWordBytes);
+            const uint2 m = meta[lane_base + c * 64];
+            const int lb = (int)(m.x >> 16);
+            const int col = (int)(m.x & 0xFFFF);
+            const int ts_j = (int)m.y;
             const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);
             int s0, s1;
-            pair_scores<LA>(V.bsym + slot * kWordBytes, lb, lbmax_w, prof, V.gap, s0, s1);
-            const int col = V.bcol[slot];
+            pair_scores_regs<LA>(bw, lb, lbmax_w, prof, V.gap, s0, s1);
             if (col == 0xFFFF) continue;
             const int64_t j = J0 + col;
-            const uint64_t thr_j = T.thr[j];
-            const int ts_j = key_score(thr_j, T.lo);
             // each unordered pair once: in a diagonal block only j > u
             const bool v0 = (r < b) || (j > u0);
             const bool v1 = u1 >= 0 && ((r < b) || (j > u1));
@@ -112,7 +136,7 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
                 }
                 if (s0 >= ts_j) {
                     const uint64_t kc = nb_key(s0, T.lo, (uint32_t)u0);
-                    if (kc >= thr_j) emit_candidate(T, j, kc);
+                    if (kc >= T.thr[j]) emit_candidate(T, j, kc);
                 }
             }
             if (v1) {
@@ -124,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
                 }
                 if (s1 >= ts_j) {
                     const uint64_t kc = nb_key(s1, T.lo, (uint32_t)u1);
-                    if (kc >= thr_j) emit_candidate(T, j, kc);
+                    if (kc >= T.thr[j]) emit_candidate(T, j, kc);
                 }
             }
         }

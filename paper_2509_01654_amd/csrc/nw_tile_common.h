@@ -100,6 +100,21 @@ __device__ __forceinline__ void load_word(uint32_t (&bw)[kWordBytes / 4], const 
     }
 }
 
+// Scores of the two row words (u, u') against a lane word already in registers.
+template <int LA>
+__device__ __forceinline__ void pair_scores_regs(const uint32_t (&bw)[kWordBytes / 4], int lb, int lbmax_w,
+                                                 const uint8_t *prof, int gap, int &s0, int &s1)
+{
+    if constexpr (LA == 0) {
+        s0 = s1 = gap * lb;
+    } else {
+        const h2 g = dp_lane<LA, kWordBytes>(bw, lbmax_w, prof, profile_stride_dw<LA>() * 4u);
+        const int off = gap * (LA + lb);
+        s0 = (int)g[0] + off;
+        s1 = (int)g[1] + off;
+    }
+}
+
 // Scores of the two row words (u, u') against the lane word of length lb:
 // the DP of nw_dp.h plus the change of variables back to Algorithm 1.
 template <int LA>
