@@ -10,6 +10,8 @@ Contents
 * ``nw_oracle.c`` (built into ``liboracle.so`` with gcc): Algorithm 1 of the
   paper literally, the row-major upper triangle, per-word top-k by full sort,
   per-query top-k, and the histogram of unordered-pair scores.
+* :func:`edges`: the pairs whose raw score or normalised weight (Section 5)
+  lies in a closed slice, filtered from the triangle in row-major order.
 * ``brute.py``: the plain definition of the score (maximum over every global
   alignment), an explicit-alignment scorer, Levenshtein distance and LCS length.
 * ``index_map.py``: the paper's row-major pair index and its inverse
@@ -179,6 +181,42 @@ def query(symbols, offsets, sim, gap, qsymbols, qoffsets, k, threads=None):
                        _p(qsymbols), _p(qoffsets), nq, k, _p(sc), _p(ix), threads or default_threads())
     assert rc == 0
     return sc, ix
+
+
+def normalised_weight(s: int, la: int, lb: int):
+    """Section 5's normalised edge weight, exactly: 100 * score / max(len A, len B)
+    as a Fraction (a pair of two empty words, score 0, has weight 0)."""
+    from fractions import Fraction
+    return Fraction(100 * int(s), max(int(la), int(lb), 1))
+
+
+def in_slice(s, la, lb, lo: int, hi: int, normalised: bool = False, den: int = 1) -> np.ndarray:
+    """Which pairs lie in the closed slice: lo <= s <= hi (raw), or
+    lo/den <= 100 s / max(la, lb, 1) <= hi/den (normalised), in exact integers."""
+    s = np.asarray(s, dtype=np.int64)
+    if not normalised:
+        return (s >= lo) & (s <= hi)
+    m = np.maximum(np.maximum(np.asarray(la, np.int64), np.asarray(lb, np.int64)), 1)
+    w = 100 * s * int(den)
+    return (w >= int(lo) * m) & (w <= int(hi) * m)
+
+
+def edges(symbols, offsets, sim, gap, lo, hi, normalised=False, den=1, idx_begin=0, idx_end=None, threads=None):
+    """Edges of the word graph whose weight lies in a closed slice (Section 5 slices
+    the graph by raw or normalised weight): (i, j, score) for the pairs i < j of
+    row-major indices [idx_begin, idx_end), in that order.  Small n only (it
+    enumerates every pair index)."""
+    offsets = _c(offsets, np.uint64)
+    n = offsets.shape[0] - 1
+    E = num_pairs(n)
+    if idx_end is None:
+        idx_end = E
+    s = triangle(symbols, offsets, sim, gap, idx_begin, idx_end, threads).astype(np.int64)
+    i, j = np.triu_indices(n, 1)            # row-major pair order (Section 4.1)
+    i, j = i[idx_begin:idx_end], j[idx_begin:idx_end]
+    lens = np.diff(offsets).astype(np.int64)
+    keep = in_slice(s, lens[i], lens[j], lo, hi, normalised, den)
+    return i[keep].astype(np.int64), j[keep].astype(np.int64), s[keep].astype(np.int32)
 
 
 def score_bounds(max_len: int, sim: np.ndarray, gap: int):
