@@ -76,7 +76,9 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
     const bool lds_hist = T.hist != nullptr && T.nbins <= kLdsHistMax;
     const uint32_t hs = hist_stride(T.nbins);
     uint32_t *hist_all = reinterpret_cast<uint32_t *>(lds + 2 * prof_bytes);
-    uint32_t *hist = hist_all + (lane & (kHistCopies - 1)) * hs;   // this lane's copy
+    // this lane's copy, indexed by the score itself (biased by lo)
+    uint32_t *hist = hist_all + (lane & (kHistCopies - 1)) * hs - T.lo;
+    const int off_a = V.gap * LA;   // score = G + gap * (LA + lb), Section 4 change of variables
     if (lds_hist)
         for (int i = tid; i < kHistCopies * (int)hs; i += kThreads) hist_all[i] = 0;
     // The column block's slots are the same for every row pair: stage their
@@ -107,28 +109,28 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
         // a key >= thr needs score >= the threshold's score: test that first
         const int ts_u0 = key_score(thr_u0, T.lo);
         const int ts_u1 = key_score(thr_u1, T.lo);
-        // the next lane word's symbols are fetched while this one runs
-        uint32_t bw_next[kWordBytes / 4];
-        load_word(bw_next, V.bsym + (J0 + lane_base) * kWordBytes);
-        for (int c = 0; c < CPL; ++c) {
-            uint32_t bw[kWordBytes / 4];
-#pragma unroll
-            for (int q = 0; q < kWordBytes / 4; ++q) bw[q] = bw_next[q];
-            if (c + 1 < CPL) load_word(bw_next, V.bsym + (J0 + lane_base + (c + 1) * 64) * kWordBytes);
+        // One column word of this lane: its DP against the row pair, then the
+        // histogram and both endpoints' candidate tests.
+        auto column = [&](const uint32_t(&bw)[kWordBytes / 4], int c) __attribute__((always_inline)) {
             const uint2 m = meta[lane_base + c * 64];
             const int lb = (int)(m.x >> 16);
             const int col = (int)(m.x & 0xFFFF);
             const int ts_j = (int)m.y;
             const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);
-            int s0, s1;
-            pair_scores_regs<LA>(bw, lb, lbmax_w, prof, V.gap, s0, s1);
-            if (col == 0xFFFF) continue;
+            h2 g;
+            if constexpr (LA == 0)
+                g = h2{0, 0};
+            else
+                g = dp_lane<LA, kWordBytes>(bw, lbmax_w, prof, profile_stride_dw<LA>() * 4u);
+            if (col == 0xFFFF) return;
+            const int off = off_a + __mul24(V.gap, lb);
+            const int s0 = (int)g[0] + off, s1 = (int)g[1] + off;
             const int64_t j = J0 + col;
             // each unordered pair once: in a diagonal block only j > u
             const bool v0 = (r < b) || (j > u0);
             const bool v1 = u1 >= 0 && ((r < b) || (j > u1));
             if (v0) {
-                if (lds_hist) atomicAdd(&hist[s0 - T.lo], 1u);
+                if (lds_hist) atomicAdd(&hist[s0], 1u);
                 else if (T.hist) atomicAdd(&T.hist[s0 - T.lo], 1ull);
                 if (s0 >= ts_u0) {
                     const uint64_t kr = nb_key(s0, T.lo, (uint32_t)j);
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
                 }
             }
             if (v1) {
-                if (lds_hist) atomicAdd(&hist[s1 - T.lo], 1u);
+                if (lds_hist) atomicAdd(&hist[s1], 1u);
                 else if (T.hist) atomicAdd(&T.hist[s1 - T.lo], 1ull);
                 if (s1 >= ts_u1) {
                     const uint64_t kr = nb_key(s1, T.lo, (uint32_t)j);
@@ -151,6 +153,21 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
                     if (kc >= T.thr[j]) emit_candidate(T, j, kc);
                 }
             }
+        };
+        // Lane words are prefetched one ahead into two alternating register
+        // sets (the loop handles two column words per trip), so no word is
+        // copied between registers; the fetch past the last word re-reads the
+        // last one.
+        const uint8_t *wbase = V.bsym + (J0 + lane_base) * kWordBytes;
+        auto word_at = [&](int c) { return wbase + (int64_t)min(c, CPL - 1) * 64 * kWordBytes; };
+        uint32_t bwA[kWordBytes / 4], bwB[kWordBytes / 4];
+        load_word(bwA, word_at(0));
+        for (int c = 0; c < CPL; c += 2) {
+            load_word(bwB, word_at(c + 1));
+            column(bwA, c);
+            if (c + 1 >= CPL) break;
+            load_word(bwA, word_at(c + 2));
+            column(bwB, c + 1);
         }
     }
     if (lds_hist) {
