@@ -7,7 +7,7 @@ one step = the whole all-pairs pass producing every word's top-32 neighbours
 (int16 score, int32 index, ties by lower index) and the global score
 histogram: n(n-1)/2 = 1.8e11 pairs, every pair scored once.
 
-    python bench.py [--steps K] [--warmup W] [--workload paper|mid] [--cpu-seconds S]
+    python bench.py [--steps K] [--warmup W] [--workload paper|mid|batched|diag|edges|export] [--cpu-seconds S]
 
 Prints one JSON line (see the design doc for every field).  --gpus N with N > 1
 exits: this build measures one GPU.
@@ -32,6 +32,39 @@ PEAK_16BIT_OPS = 256 * 64 * 2 * 2.4e9
 OPS_PER_CELL = 5            # 2 adds, 2 maxes, 1 similarity per DP cell (Algorithm 1)
 # VALU issue ceiling of the kernel's instruction sequence: one lane-instruction per cell
 PEAK_ISSUE_CELLS = 256 * 64 * 2.4e9
+
+# HBM bytes of the main pass from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, kept in
+# this summary together with the SHA-256 of the sources the kernel was built from
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "topk_main_paper600k_counters.md")
+MAIN_PASS_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "nw_topk.h", "k_topk.h", "k_query.h",
+                     "k_launch.hip", "k_inst.hip", "nw_api.cpp"]
+
+
+def main_pass_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in MAIN_PASS_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_01654_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """(bytes fetched, bytes written) per main pass from the counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    try:
+        text = open(COUNTER_SUMMARY, encoding="utf-8").read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("traffic:"):
+            for kv in line[len("traffic:"):].split():
+                k, _, val = kv.partition("=")
+                fields[k] = val
+    if fields.get("sources_sha256") != main_pass_sources_sha256():
+        return None
+    return float(fields["fetch_bytes"]), float(fields["write_bytes"])
 
 
 def host_cpu_model() -> str:
@@ -206,12 +239,91 @@ def bench_diag(args, nw, synth, torch, dev):
                            "gcups": round(dl.num_cells / t_long / 1e6, 1)}}
 
 
+def bench_edges(args, nw, synth, torch, dev):
+    """Threshold edges of the 600,000-word dictionary in the normalised slice
+    [60, 100] (the slice of the paper's ego networks): every pair scored, the
+    passing pairs appended as (i, j, score)."""
+    v = synth.plain_config("paper")
+    dv = nw.Vocab(v.symbols, v.offsets, nw.Scoring(40, 1, -1, -1), device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    _, _, _, total = dv.all_pairs_edges(60, 100, True, 1, cap=0, count=cnt)
+    cap = total + 1024
+    out = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+           torch.empty(cap, dtype=torch.int16, device=dev))
+
+    def step():
+        return dv.all_pairs_edges(60, 100, True, 1, cap=cap, out=out, count=cnt)[3]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    assert c == total
+    cells, E = dv.num_cells, dv.num_pairs
+    achieved = OPS_PER_CELL * cells / (ms / 1e3)
+    return {"metric": METRIC, "value": round(cells / (ms / 1e3) / 1e9, 1), "unit": "GCUPS", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+            "pairs_per_s": E / (ms / 1e3),
+            "config": {"workload": "threshold edges, normalised weight in [60, 100], 600,000 words (Zipf-40, "
+                                   "clip(Poisson 8, 1, 32), +1/-1, gap -1)", "n_words": dv.n, "pairs": E,
+                       "cells": cells, "edges": total},
+            "edges_per_s": total / (ms / 1e3), "edge_bytes_per_s": 10 * total / (ms / 1e3),
+            "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2),
+                         "peak": round(PEAK_16BIT_OPS / 1e12, 2), "unit": "Tops/s (16-bit)",
+                         "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
+                         "kernel": "k_tri_tiled (edge mode, every LA)",
+                         "issue_frac": round(cells / (ms / 1e3) / PEAK_ISSUE_CELLS, 4)}}
+
+
+def bench_export(args, nw, synth, torch, dev):
+    """The whole int8 triangle of the 600,000-word dictionary streamed to page-
+    locked host memory in 1 GiB chunks (nw_export_triangle); the consumer only
+    touches each chunk.  The rate includes the device-to-host copies."""
+    v = synth.plain_config("paper")
+    dv = nw.Vocab(v.symbols, v.offsets, nw.Scoring(40, 1, -1, -1), device=dev)
+    chunk = 1 << 30
+    ws = torch.empty(2 * chunk, dtype=torch.uint8, device=dev)
+    host = torch.empty(2 * chunk, dtype=torch.uint8, pin_memory=True)
+    got = [0]
+
+    def consume(b0, scores):
+        got[0] += len(scores)
+
+    def step():
+        dv.export_triangle(consume, dtype=torch.int8, chunk_pairs=chunk, ws=ws, host=host)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    got[0] = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    E, cells = dv.num_pairs, dv.num_cells
+    assert got[0] == E * args.steps
+    return {"metric": METRIC, "value": round(cells / (ms / 1e3) / 1e9, 1), "unit": "GCUPS", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+            "pairs_per_s": E / (ms / 1e3),
+            "config": {"workload": "streamed int8 triangle export to host, 600,000 words (Zipf-40, clip(Poisson 8, "
+                                   "1, 32), +1/-1, gap -1), 1 GiB chunks", "n_words": dv.n, "pairs": E,
+                       "cells": cells, "bytes": E},
+            "host_GB_per_s": round(E / (ms / 1e3) / 1e9, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["paper", "mid", "batched", "diag"], default="paper")
+    ap.add_argument("--workload", choices=["paper", "mid", "batched", "diag", "edges", "export"], default="paper")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-rates", default="10000,50000",
@@ -247,6 +359,12 @@ def main():
         return
     if args.workload == "diag":
         print(json.dumps(bench_diag(args, nw, synth, torch, dev)), flush=True)
+        return
+    if args.workload == "edges":
+        print(json.dumps(bench_edges(args, nw, synth, torch, dev)), flush=True)
+        return
+    if args.workload == "export":
+        print(json.dumps(bench_export(args, nw, synth, torch, dev)), flush=True)
         return
     v = synth.plain_config(args.workload)
     dv = nw.Vocab(v.symbols, v.offsets, nw.Scoring(40, 1, -1, -1), device=dev)
@@ -309,10 +427,18 @@ def main():
         rec["phase_ms"] = {"threshold_prepass": round(pre, 3), "main_pass": round(main_ms, 3),
                            "select": round(sel, 3)}
         achieved = OPS_PER_CELL * cells / (main_ms / 1e3)
+        tr = counter_traffic()
         rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
-                           "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
+                           "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4),
+                           "traffic": None if tr is None else round(tr[0] + tr[1]),
                            "kernel": "k_topk_tiled (all-pairs main pass, every LA)",
                            "issue_frac": round(cells / (main_ms / 1e3) / PEAK_ISSUE_CELLS, 4)}
+        if tr is not None:
+            rec["roofline"]["traffic_detail"] = {
+                "unit": "HBM bytes per main pass (calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                "fetch": round(tr[0]), "write": round(tr[1]),
+                "GB_per_s": round((tr[0] + tr[1]) / (main_ms / 1e3) / 1e9, 1),
+                "frac_of_hbm_peak": round((tr[0] + tr[1]) / (main_ms / 1e3) / 8e12, 4)}
         if args.serve_rates:
             rec["served"] = serve(nw, dv, [float(r) for r in args.serve_rates.split(",")], args.serve_queries,
                                   rec["phase_ms"]["main_pass"], cells)

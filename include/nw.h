@@ -39,7 +39,8 @@ enum {
     NW_EINVAL = -1,   /* invalid argument (symbol >= alphabet, word too long, gap > 0, ...) */
     NW_ERANGE = -2,   /* scores or DP values do not fit the requested/internal type       */
     NW_ENOMEM = -3,   /* the memory handed in is smaller than the *_bytes query says       */
-    NW_EDEVICE = -4   /* the HIP runtime reported an error                                 */
+    NW_EDEVICE = -4,  /* the HIP runtime reported an error                                 */
+    NW_ESTOPPED = -5  /* a caller callback asked the call to stop                          */
 };
 
 typedef enum { NW_I8 = 1, NW_I16 = 2 } nw_dtype;
@@ -125,6 +126,72 @@ int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx
  * comparison point for the tiled kernels; same arguments and errors. */
 int nw_all_pairs_scores_naive(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
                               void *d_out, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Streamed triangle export.  Section 5 stops at about 107,000 words because
+ * the whole i8 edge-weight array must fit the GPU, and proposes copying parts
+ * of it to the host and continuing with the index shifted back to 0.  This
+ * call does that for any range of pair indices: the triangle is computed in
+ * chunks of chunk_pairs pairs into two alternating device buffers while the
+ * previous chunk is copied to the host on a second stream, and each chunk
+ * is handed to the caller in index order.
+ * ------------------------------------------------------------------------- */
+
+/* Receives the scores of pair indices [idx_begin, idx_begin + count) in the
+ * export's dtype.  h_chunk is valid only during the call.  Return 0 to go on,
+ * anything else to stop the export. */
+typedef int (*nw_chunk_fn)(void *user, uint64_t idx_begin, uint64_t count, const void *h_chunk);
+
+/* Scores of pair indices [idx_begin, idx_end), the same values and order as
+ * nw_all_pairs_scores, delivered through fn (called on the calling thread,
+ * once per chunk, in index order; the last chunk may be shorter).
+ * d_ws: device memory of 2 * chunk_pairs * sizeof(dt) bytes, 256-byte aligned.
+ * h_buf: host memory of the same size; page-locked memory (hipHostMalloc)
+ * gives the full transfer rate.  Both are caller-owned and reused in turn.
+ * Work is enqueued on hip_stream (kernels) and on a stream the call creates
+ * and destroys (copies).  Synchronous: returns once the last chunk has been
+ * delivered, or after a stop with every enqueued step finished.
+ * Errors: NW_EINVAL (as nw_all_pairs_scores, NULL fn, d_ws or h_buf with a
+ * non-empty range, chunk_pairs == 0, misaligned d_ws), NW_ERANGE (scores do
+ * not fit int8), NW_ESTOPPED (fn returned non-zero), NW_EDEVICE. */
+int nw_export_triangle(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, uint64_t chunk_pairs,
+                       void *d_ws, void *h_buf, nw_chunk_fn fn, void *user, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Threshold edges (graph export).  Section 5 slices the word graph by edge
+ * weight before drawing it: raw alignment scores, or scores normalised by the
+ * longer word, weight(i, j) = 100 * score(i, j) / max(len i, len j).
+ * ------------------------------------------------------------------------- */
+
+typedef enum { NW_EDGE_RAW = 0, NW_EDGE_NORMALISED = 1 } nw_edge_mode;
+
+/* A closed slice of edge weights.  NW_EDGE_RAW: lo <= score <= hi (den is
+ * ignored).  NW_EDGE_NORMALISED: lo/den <= weight <= hi/den, decided exactly
+ * in integers as lo*m <= 100*score*den <= hi*m, m = max(len i, len j, 1)
+ * (a pair of two empty words has weight 0).  den in 1..1000000 lets a slice
+ * end between integers (200/3 is lo = hi = 200, den = 3). */
+typedef struct {
+    int32_t mode;
+    int32_t lo, hi;
+    int32_t den;
+} nw_edge_filter;
+
+/* Every unordered pair (i, j), i < j, with pair index in [idx_begin, idx_end)
+ * (the row-major order of nw_all_pairs_scores) whose weight lies in the slice
+ * *f is appended as (d_i[q], d_j[q], d_score[q]) = (i, j, score(i, j)),
+ * q = 0, 1, ...  in no particular order (one run may order the edges
+ * differently from the next; the set is exact).  *d_count (device uint64,
+ * set by this call) receives the number of pairs that passed; when it exceeds
+ * cap only cap of them are stored and the caller repeats with a larger cap
+ * or a smaller index range.  d_i, d_j (int32) and d_score (int16) hold cap
+ * entries each (they may be NULL when cap == 0, to count only).  Enqueued
+ * on hip_stream; the results are valid once it has synchronised.
+ * Errors: NW_EINVAL (NULL vocab, filter or d_count, d_count not 8-byte or
+ * the arrays not naturally aligned, mode not one of nw_edge_mode, lo > hi, den outside 1..1000000 for the normalised mode, a
+ * range outside [0, n(n-1)/2], an asymmetric similarity), NW_EDEVICE. */
+int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, const nw_edge_filter *f,
+                       int32_t *d_i, int32_t *d_j, int16_t *d_score, uint64_t cap, uint64_t *d_count,
+                       void *hip_stream);
 
 
 /* ---------------------------------------------------------------------------
@@ -261,6 +328,38 @@ void nw_batch_destroy(nw_batch *b);
 int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, nw_dtype dt, void *d_ws,
                       uint64_t ws_bytes, void *hip_stream, const char *cache_path, nw_batch_options *best,
                       float *best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Ego networks on the word graph.  Section 5 reads the graph through
+ * ego networks: the words within a few hops (depth 3 in its figures) of a
+ * chosen word, in a slice of edge weights.  These calls take an edge list
+ * (for instance from nw_all_pairs_edges) as an undirected graph on n words.
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes of nw_graph_csr for n nodes. */
+int nw_graph_workspace_bytes(uint64_t n, uint64_t *bytes);
+
+/* Compressed rows of the undirected graph with the m edges {d_i[e], d_j[e]}:
+ * the neighbours of node v are d_adj[d_row_ptr[v] .. d_row_ptr[v+1]), each
+ * edge listed from both ends (a self-loop twice at its node, a repeated edge
+ * as often as it is given), in no particular order within a row.
+ * d_row_ptr: n+1 int64; d_adj: 2m int32; d_ws: nw_graph_workspace_bytes,
+ * 256-byte aligned.  All device memory, caller-owned.  Synchronous (it reads
+ * back the endpoint check).
+ * Errors: NW_EINVAL (n >= 2^31, NULL or misaligned arguments, an endpoint
+ * outside [0, n)), NW_ENOMEM (ws_bytes too small), NW_EDEVICE. */
+int nw_graph_csr(uint64_t n, const int32_t *d_i, const int32_t *d_j, uint64_t m, int64_t *d_row_ptr, int32_t *d_adj,
+                 void *d_ws, uint64_t ws_bytes, void *hip_stream);
+
+/* Hop distances from a seed set, breadth first, up to `depth` hops:
+ * d_dist[v] (int32, n entries, device) = the fewest edges on a path from any
+ * seed to v if that is <= depth (0 for the seeds), else -1.  The nodes with
+ * d_dist >= 0 are the ego network of the seeds.  h_seeds: host array of
+ * n_seeds node ids (repeats allowed).  Enqueued on hip_stream.
+ * Errors: NW_EINVAL (NULL arguments, n >= 2^31, a seed outside [0, n),
+ * depth > 1000000), NW_EDEVICE. */
+int nw_ego_network(uint64_t n, const int64_t *d_row_ptr, const int32_t *d_adj, const int32_t *h_seeds,
+                   uint32_t n_seeds, uint32_t depth, int32_t *d_dist, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnw.so")
 
-NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOMEM, NW_EDEVICE = 0, -1, -2, -3, -4
+NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOMEM, NW_EDEVICE, NW_ESTOPPED = 0, -1, -2, -3, -4, -5
 NW_I8, NW_I16 = 1, 2
 
 _lib = None
@@ -30,6 +30,17 @@ class NwError(RuntimeError):
 class _Scoring(ctypes.Structure):
     _fields_ = [("alphabet", ctypes.c_int32), ("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
                 ("gap", ctypes.c_int32), ("submat", ctypes.c_void_p)]
+
+
+class _EdgeFilter(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("lo", ctypes.c_int32), ("hi", ctypes.c_int32), ("den", ctypes.c_int32)]
+
+
+NW_EDGE_RAW, NW_EDGE_NORMALISED = 0, 1
+
+
+# nw_chunk_fn: int (*)(void *user, uint64_t idx_begin, uint64_t count, const void *h_chunk)
+_CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p)
 
 
 class _BatchOptions(ctypes.Structure):
@@ -68,6 +79,11 @@ def load_library(path: str = LIB_PATH):
         "nw_topk_phase_times": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                                ctypes.POINTER(ctypes.c_float)]),
         "nw_query": (ctypes.c_int, [P, P, P, u64, u32, P, P, P, u64, P]),
+        "nw_all_pairs_edges": (ctypes.c_int, [P, u64, u64, ctypes.POINTER(_EdgeFilter), P, P, P, u64, P, P]),
+        "nw_export_triangle": (ctypes.c_int, [P, u64, u64, ctypes.c_int, u64, P, P, _CHUNK_FN, P, P]),
+        "nw_graph_workspace_bytes": (ctypes.c_int, [u64, ctypes.POINTER(u64)]),
+        "nw_graph_csr": (ctypes.c_int, [u64, P, P, u64, P, P, P, u64, P]),
+        "nw_ego_network": (ctypes.c_int, [u64, P, P, P, u32, u32, P, P]),
     }
     sig.update({
         "nw_server_workspace_bytes": (ctypes.c_int, [P, u32, u32, u32, ctypes.POINTER(u64)]),
@@ -115,6 +131,40 @@ def vocab_bytes(n: int, total_symbols: int, max_len: int) -> int:
     out = ctypes.c_uint64()
     _check(lib.nw_vocab_bytes(n, total_symbols, max_len, ctypes.byref(out)))
     return out.value
+
+
+def graph_csr(n: int, i, j, stream=None):
+    """Compressed rows of the undirected graph with edges {i[e], j[e]} on n nodes
+    (nw_graph_csr): (row_ptr int64 [n+1], adj int32 [2m]) on the edges' device."""
+    import torch
+    lib = load_library()
+    m = i.numel()
+    assert j.numel() == m and i.dtype == j.dtype == torch.int32 and i.is_contiguous() and j.is_contiguous()
+    dev = i.device
+    nbytes = ctypes.c_uint64()
+    _check(lib.nw_graph_workspace_bytes(n, ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    adj = torch.empty(max(2 * m, 1), dtype=torch.int32, device=dev)
+    _check(lib.nw_graph_csr(n, ctypes.c_void_p(i.data_ptr()), ctypes.c_void_p(j.data_ptr()), m,
+                            ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(adj.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), nbytes.value, _stream_handle(stream)))
+    return row_ptr, adj[:2 * m]
+
+
+def ego_network(row_ptr, adj, seeds, depth: int, out=None, stream=None):
+    """Hop distance of every node from the seed set, -1 beyond `depth` (nw_ego_network)."""
+    import torch
+    lib = load_library()
+    n = row_ptr.numel() - 1
+    seeds = np.ascontiguousarray(np.asarray(seeds, dtype=np.int32))
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=row_ptr.device)
+    ap = ctypes.c_void_p(adj.data_ptr()) if adj.numel() else None
+    _check(lib.nw_ego_network(n, ctypes.c_void_p(row_ptr.data_ptr()), ap,
+                              seeds.ctypes.data if seeds.size else None, seeds.size, depth,
+                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
 
 
 class Scoring:
@@ -190,6 +240,84 @@ class Vocab:
         """Same output through the intra-pair anti-diagonal kernel."""
         import torch
         return self._triangle(_lib.nw_all_pairs_scores_diag, idx_begin, idx_end, dtype or torch.int8, out, stream)
+
+    # ----------------------------------------------------------------- export
+    def export_triangle(self, fn, dtype=None, chunk_pairs: int = 1 << 28, idx_begin: int = 0,
+                        idx_end: int | None = None, ws=None, host=None, stream=None):
+        """Stream the triangle of pair indices [idx_begin, idx_end) to the host in
+        chunks (nw_export_triangle): fn(idx_begin, scores) is called once per chunk,
+        in index order, with a numpy view that is valid only during the call;
+        a truthy return value stops the export (NwError NW_ESTOPPED).  ws (device)
+        and host (page-locked) buffers of 2*chunk_pairs elements are allocated
+        when not given."""
+        import torch
+        dtype = dtype or torch.int8
+        if idx_end is None:
+            idx_end = self.num_pairs
+        dt = {torch.int8: NW_I8, torch.int16: NW_I16}[dtype]
+        np_dtype = np.int8 if dt == NW_I8 else np.int16
+        es = 1 if dt == NW_I8 else 2
+        chunk_pairs = max(1, min(chunk_pairs, max(1, idx_end - idx_begin)))
+        nbytes = 2 * chunk_pairs * es
+        if ws is None or ws.numel() * ws.element_size() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if host is None or host.numel() * host.element_size() < nbytes:
+            host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        raised = []
+
+        def chunk(_user, b0, count, ptr):
+            try:
+                view = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_int8 if es == 1
+                                                                              else ctypes.c_int16)), (count,))
+                return 1 if fn(b0, view.view(np_dtype)) else 0
+            except BaseException as exc:  # stop the export and re-raise below
+                raised.append(exc)
+                return 1
+
+        cb = _CHUNK_FN(chunk)
+        rc = _lib.nw_export_triangle(self._h, idx_begin, idx_end, dt, chunk_pairs, ctypes.c_void_p(ws.data_ptr()),
+                                     ctypes.c_void_p(host.data_ptr()), cb, None, _stream_handle(stream))
+        if raised:
+            raise raised[0]
+        _check(rc)
+
+    # ------------------------------------------------------------------ edges
+    def all_pairs_edges(self, lo: int, hi: int, normalised: bool = False, den: int = 1, cap: int | None = None,
+                        idx_begin: int = 0, idx_end: int | None = None, out=None, count=None, stream=None):
+        """Pairs (i < j) whose raw score, or normalised weight 100*s/max(len i, len j)
+        when `normalised`, lies in the closed slice [lo/den, hi/den] (nw_all_pairs_edges).
+
+        Returns (i int32, j int32, score int16, count): the arrays hold the first
+        min(count, cap) edges, in no particular order; count is the number of pairs
+        that passed (it exceeds cap when the arrays were too small).  With cap=None
+        a counting call sizes the arrays first.  `count` may pass a one-element int64
+        device tensor to reuse for the count.  Synchronises the stream.
+        """
+        import torch
+        if idx_end is None:
+            idx_end = self.num_pairs
+        f = _EdgeFilter(NW_EDGE_NORMALISED if normalised else NW_EDGE_RAW, lo, hi, den)
+        cnt = count if count is not None else torch.empty(1, dtype=torch.int64, device=self.device)
+        sh = _stream_handle(stream)
+
+        def run(i, j, sc, c):
+            P = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None)
+            _check(_lib.nw_all_pairs_edges(self._h, idx_begin, idx_end, ctypes.byref(f), P(i), P(j), P(sc), c,
+                                           ctypes.c_void_p(cnt.data_ptr()), sh))
+            (stream or torch.cuda.current_stream()).synchronize()
+            return int(cnt.item())
+
+        if cap is None:
+            cap = run(None, None, None, 0) if out is None else out[0].numel()
+        if out is None:
+            out = (torch.empty(cap, dtype=torch.int32, device=self.device),
+                   torch.empty(cap, dtype=torch.int32, device=self.device),
+                   torch.empty(cap, dtype=torch.int16, device=self.device))
+        i, j, sc = out
+        assert i.numel() >= cap and j.numel() >= cap and sc.numel() >= cap
+        count = run(i, j, sc, cap)
+        m = min(count, cap)
+        return i[:m], j[:m], sc[:m], count
 
     # ------------------------------------------------------------------ top-k
     def topk_workspace_bytes(self, k: int) -> int:

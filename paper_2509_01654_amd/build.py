@@ -42,6 +42,8 @@ def _units():
         ("nw_api", os.path.join(CSRC, "nw_api.cpp"), []),
         ("nw_server", os.path.join(CSRC, "nw_server.cpp"), []),
         ("nw_batch", os.path.join(CSRC, "nw_batch.cpp"), []),
+        ("nw_export", os.path.join(CSRC, "nw_export.cpp"), []),
+        ("nw_graph", os.path.join(CSRC, "nw_graph.hip"), []),
         ("k_launch", os.path.join(CSRC, "k_launch.hip"), []),
     ]
     for lo, hi in _la_splits():

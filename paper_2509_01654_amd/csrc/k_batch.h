@@ -30,7 +30,7 @@ __device__ __forceinline__ void tri_tile_dispatch(int la, const DevVocab &V, con
 {
     if constexpr (L <= HI) {
         if (la == L)
-            tri_tile<L>(V, I.r, I.b, I.pbeg, I.pend, 0, ~0ull, out, out_kind, lds);
+            tri_tile<L>(V, I.r, I.b, I.pbeg, I.pend, 0, ~0ull, out, out_kind, EdgeSink{}, lds);
         else
             tri_tile_dispatch<L + 1, HI>(la, V, I, out, out_kind, lds);
     }

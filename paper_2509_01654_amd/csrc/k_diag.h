@@ -46,14 +46,14 @@ __device__ __forceinline__ uint32_t dpp_row_shr1(uint32_t v)
 
 template <int R>
 __global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
-                                                       int out_kind, int LA)
+                                                       int out_kind, EdgeSink E, int LA, uint32_t rb0, uint32_t rbn)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr uint32_t S = diag_stride_dw(R);
     constexpr int ROWS = kDiagLanes * R;
 
     uint32_t r, b;
-    decode_block_pair(blockIdx.x, r, b);
+    if (!tile_block_pair(rb0, rbn, V.nb, r, b)) return;
     const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
     const uint32_t pbeg = rpo[0], pend = rpo[1];
     if (pbeg >= pend) return;
@@ -106,17 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_
                 if (slot < 0) continue;
                 const int64_t u = I0 + V.bcol[slot];
                 const int64_t jstart = (r == b) ? u + 1 : J0;
-                const uint64_t base = row_start_idx(n, u) + (uint64_t)(jstart - u - 1);
-                for (int64_t q = tid; q < J1 - jstart; q += kThreads) {
-                    const uint64_t idx = base + (uint64_t)q;
-                    if (idx >= idx_begin && idx < idx_end) {
-                        const int16_t s = srow[h * CB + (jstart - J0) + q];
-                        if (out_kind == OUT_I8)
-                            static_cast<int8_t *>(out)[idx - idx_begin] = (int8_t)s;
-                        else
-                            static_cast<int16_t *>(out)[idx - idx_begin] = s;
-                    }
-                }
+                store_row(V, u, LA, jstart, J1, srow + h * CB + (jstart - J0), idx_begin, idx_end, out, out_kind, E);
             }
         }
         __syncthreads();

@@ -84,19 +84,50 @@ static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, hipStream_t 
     return hipLaunchKernel(fn, grid, dim3(kThreads), args, lds, stream);
 }
 
+// Row of pair index idx in the row-major triangle of n words: the largest u
+// with S_{u-1} = (n-1)u - u(u-1)/2 <= idx (Section 4.2), by bisection.
+static int64_t row_of_index(int64_t n, uint64_t idx)
+{
+    auto start = [n](int64_t u) { return (uint64_t)(n - 1) * (uint64_t)u - (uint64_t)u * (uint64_t)(u - 1) / 2u; };
+    int64_t lo = 0, hi = n - 2;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (start(mid) <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Grid of a triangle launch over pair indices [idx_begin, idx_end): the whole
+// column-major block-pair space, or a row-major window over the block rows
+// the range touches when that is smaller.
+struct TriGrid {
+    uint32_t blocks, rb0, rbn;
+};
+static TriGrid tri_grid(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end)
+{
+    const uint64_t all = (uint64_t)V.nb * (V.nb + 1) / 2;
+    const uint32_t r0 = (uint32_t)(row_of_index(V.n, idx_begin) / V.CB);
+    const uint32_t r1 = (uint32_t)(row_of_index(V.n, idx_end - 1) / V.CB);
+    const uint64_t win = (uint64_t)(r1 - r0 + 1) * (uint64_t)V.nb;
+    if (win < all) return {(uint32_t)win, r0, r1 - r0 + 1};
+    return {(uint32_t)all, 0, 0};
+}
+
 hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
-                                 hipStream_t stream)
+                                 hipStream_t stream, const EdgeSink *E)
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
-    const uint32_t nblk_pairs = (uint32_t)((uint64_t)V.nb * (V.nb + 1) / 2);
+    const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
     for (int LA = 0; LA <= V.lmax; ++LA) {
         DevVocab Vc = V;
         uint64_t ib = idx_begin, ie = idx_end;
         void *po = d_out;
         int ok = out_kind;
-        void *args[] = {&Vc, &ib, &ie, &po, &ok};
-        hipError_t e = launch_dyn(tab.tri[LA], dim3(nblk_pairs), tri_lds_bytes(LA, V.alphabet, V.CB), stream, args);
+        EdgeSink es = E ? *E : EdgeSink{};
+        uint32_t rb0 = G.rb0, rbn = G.rbn;
+        void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn};
+        hipError_t e = launch_dyn(tab.tri[LA], dim3(G.blocks), tri_lds_bytes(LA, V.alphabet, V.CB), stream, args);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -127,20 +158,22 @@ hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t
 }
 
 hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
-                                hipStream_t stream)
+                                hipStream_t stream, const EdgeSink *E)
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
-    const uint32_t nblk_pairs = (uint32_t)((uint64_t)V.nb * (V.nb + 1) / 2);
+    const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
     for (int LA = 0; LA <= V.lmax; ++LA) {
         DevVocab Vc = V;
         uint64_t ib = idx_begin, ie = idx_end;
         void *po = d_out;
         int ok = out_kind;
+        EdgeSink es = E ? *E : EdgeSink{};
+        uint32_t rb0 = G.rb0, rbn = G.rbn;
         hipError_t e;
         if (LA == 0) {
-            void *args[] = {&Vc, &ib, &ie, &po, &ok};
-            e = launch_dyn(tab.tri[0], dim3(nblk_pairs), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
+            void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn};
+            e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
         } else {
             // rows per lane: the smallest class whose 16 lanes cover LA rows
             const int R = LA <= 64 ? 4 : LA <= 128 ? 8 : LA <= 192 ? 12 : 16;
@@ -149,8 +182,8 @@ hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t 
                            : R == 12 ? reinterpret_cast<const void *>(&k_tri_diag<12>)
                                      : reinterpret_cast<const void *>(&k_tri_diag<16>);
             int la = LA;
-            void *args[] = {&Vc, &ib, &ie, &po, &ok, &la};
-            e = launch_dyn(fn, dim3(nblk_pairs), diag_lds_bytes(R, V.alphabet, V.CB), stream, args);
+            void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &la, &rb0, &rbn};
+            e = launch_dyn(fn, dim3(G.blocks), diag_lds_bytes(R, V.alphabet, V.CB), stream, args);
         }
         if (e != hipSuccess) return e;
     }

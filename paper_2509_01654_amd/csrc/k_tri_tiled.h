@@ -22,11 +22,12 @@ namespace nw {
 
 // One tile: row pairs [pbeg, pend) of block r (all of length LA) against the
 // columns of block b, scores of pair indices in [idx_begin, idx_end) stored to
-// `out` (int8 or int16).  All threads of the workgroup must call it; it ends
+// `out` (int8 or int16) or, for OUT_EDGES, filtered into the edge sink E.  All threads of the workgroup must call it; it ends
 // with a barrier, so the caller may reuse the LDS afterwards.
 template <int LA>
 __device__ __forceinline__ void tri_tile(const DevVocab &V, uint32_t r, uint32_t b, uint32_t pbeg, uint32_t pend,
-                                         uint64_t idx_begin, uint64_t idx_end, void *out, int out_kind, uint8_t *lds)
+                                         uint64_t idx_begin, uint64_t idx_end, void *out, int out_kind,
+                                         const EdgeSink &E, uint8_t *lds)
 {
     if (pbeg >= pend) return;
 
@@ -68,17 +69,7 @@ __device__ __forceinline__ void tri_tile(const DevVocab &V, uint32_t r, uint32_t
                 if (slot < 0) continue;
                 const int64_t u = I0 + V.bcol[slot];
                 const int64_t jstart = (r == b) ? u + 1 : J0;
-                const uint64_t base = row_start_idx(n, u) + (uint64_t)(jstart - u - 1);
-                for (int64_t t = tid; t < J1 - jstart; t += kThreads) {
-                    const uint64_t idx = base + (uint64_t)t;
-                    if (idx >= idx_begin && idx < idx_end) {
-                        const int16_t s = srow[h * CB + (jstart - J0) + t];
-                        if (out_kind == OUT_I8)
-                            static_cast<int8_t *>(out)[idx - idx_begin] = (int8_t)s;
-                        else
-                            static_cast<int16_t *>(out)[idx - idx_begin] = s;
-                    }
-                }
+                store_row(V, u, LA, jstart, J1, srow + h * CB + (jstart - J0), idx_begin, idx_end, out, out_kind, E);
             }
         }
         __syncthreads();
@@ -104,13 +95,13 @@ __device__ __forceinline__ void tri_tile(const DevVocab &V, uint32_t r, uint32_t
 
 template <int LA>
 __global__ __launch_bounds__(kThreads) void k_tri_tiled(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
-                                                        int out_kind)
+                                                        int out_kind, EdgeSink E, uint32_t rb0, uint32_t rbn)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t r, b;
-    decode_block_pair(blockIdx.x, r, b);
+    if (!tile_block_pair(rb0, rbn, V.nb, r, b)) return;
     const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
-    tri_tile<LA>(V, r, b, rpo[0], rpo[1], idx_begin, idx_end, out, out_kind, lds);
+    tri_tile<LA>(V, r, b, rpo[0], rpo[1], idx_begin, idx_end, out, out_kind, E, lds);
 }
 
 }  // namespace nw

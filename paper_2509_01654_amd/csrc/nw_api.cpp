@@ -246,6 +246,30 @@ ColSet full_colset(const DevVocab &D)
 
 using namespace nw::host;
 
+int nw::host::check_triangle_args(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
+                                  const void *d_out)
+{
+    if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    if (dt != NW_I8 && dt != NW_I16) return fail(NW_EINVAL, "dtype must be NW_I8 or NW_I16");
+    if (idx_begin > idx_end || idx_end > v->num_pairs)
+        return fail(NW_EINVAL, "pair range [%llu, %llu) outside [0, %llu]", (unsigned long long)idx_begin,
+                    (unsigned long long)idx_end, (unsigned long long)v->num_pairs);
+    if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
+    if (dt == NW_I8 && (v->lo < -128 || v->hi > 127))
+        return fail(NW_ERANGE, "score bounds [%d, %d] do not fit int8", v->lo, v->hi);
+    if (idx_end > idx_begin && !d_out) return fail(NW_EINVAL, "d_out is NULL");
+    return NW_OK;
+}
+
+hipError_t nw::host::launch_triangle(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, void *d_out,
+                                     hipStream_t stream)
+{
+    // words longer than the register-row limit take the anti-diagonal kernel
+    const int kind = dt == NW_I8 ? OUT_I8 : OUT_I16;
+    return v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, idx_begin, idx_end, kind, d_out, stream)
+                                          : launch_triangle_tiled(v->dev, idx_begin, idx_end, kind, d_out, stream);
+}
+
 extern "C" {
 
 const char *nw_last_error(void) { return g_err.c_str(); }
@@ -500,34 +524,17 @@ int nw_score_bounds(const nw_vocab *v, int32_t *lo, int32_t *hi)
     return ok();
 }
 
-static int check_triangle_args(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, void *d_out)
-{
-    if (!v) return fail(NW_EINVAL, "vocab is NULL");
-    if (dt != NW_I8 && dt != NW_I16) return fail(NW_EINVAL, "dtype must be NW_I8 or NW_I16");
-    if (idx_begin > idx_end || idx_end > v->num_pairs)
-        return fail(NW_EINVAL, "pair range [%llu, %llu) outside [0, %llu]", (unsigned long long)idx_begin,
-                    (unsigned long long)idx_end, (unsigned long long)v->num_pairs);
-    if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
-    if (dt == NW_I8 && (v->lo < -128 || v->hi > 127))
-        return fail(NW_ERANGE, "score bounds [%d, %d] do not fit int8", v->lo, v->hi);
-    if (idx_end > idx_begin && !d_out) return fail(NW_EINVAL, "d_out is NULL");
-    return NW_OK;
-}
 
 int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, void *d_out,
                         void *hip_stream)
 {
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
     if (rc) return rc;
-    // words longer than the register-row limit take the anti-diagonal kernel
-    hipError_t e = v->max_len > (uint32_t)kMaxLen
-                       ? launch_triangle_diag(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
-                                              (hipStream_t)hip_stream)
-                       : launch_triangle_tiled(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
-                                               (hipStream_t)hip_stream);
+    hipError_t e = launch_triangle(v, idx_begin, idx_end, dt, d_out, (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the triangle kernels");
     return ok();
 }
+
 
 int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, void *d_out,
                              void *hip_stream)
@@ -548,6 +555,44 @@ int nw_all_pairs_scores_naive(const nw_vocab *v, uint64_t idx_begin, uint64_t id
     hipError_t e = launch_triangle_naive(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
                                          (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the naive triangle kernel");
+    return ok();
+}
+
+
+int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, const nw_edge_filter *f,
+                       int32_t *d_i, int32_t *d_j, int16_t *d_score, uint64_t cap, uint64_t *d_count,
+                       void *hip_stream)
+{
+    if (!v || !f || !d_count) return fail(NW_EINVAL, "NULL vocab, filter or count");
+    if (f->mode != NW_EDGE_RAW && f->mode != NW_EDGE_NORMALISED)
+        return fail(NW_EINVAL, "edge filter mode %d is not NW_EDGE_RAW or NW_EDGE_NORMALISED", f->mode);
+    if (f->lo > f->hi) return fail(NW_EINVAL, "edge slice [%d, %d] is empty", f->lo, f->hi);
+    if (f->mode == NW_EDGE_NORMALISED && (f->den < 1 || f->den > 1000000))
+        return fail(NW_EINVAL, "edge slice denominator %d outside 1..1000000", f->den);
+    if (cap > 0 && (!d_i || !d_j || !d_score)) return fail(NW_EINVAL, "NULL edge array with cap > 0");
+    if (((uintptr_t)d_count & 7) || ((uintptr_t)d_i & 3) || ((uintptr_t)d_j & 3) || ((uintptr_t)d_score & 1))
+        return fail(NW_EINVAL, "misaligned edge count or edge arrays");
+    if (idx_begin > idx_end || idx_end > v->num_pairs)
+        return fail(NW_EINVAL, "pair range [%llu, %llu) outside [0, %llu]", (unsigned long long)idx_begin,
+                    (unsigned long long)idx_end, (unsigned long long)v->num_pairs);
+    if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
+
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = launch_reset_counters(reinterpret_cast<uint32_t *>(d_count), 2, st);
+    if (e != hipSuccess) return dev_fail(e, "clearing the edge counter");
+    EdgeSink E{};
+    E.ei = d_i;
+    E.ej = d_j;
+    E.es = d_score;
+    E.count = reinterpret_cast<unsigned long long *>(d_count);
+    E.cap = cap;
+    E.normalised = f->mode == NW_EDGE_NORMALISED;
+    E.lo = f->lo;
+    E.hi = f->hi;
+    E.den = f->mode == NW_EDGE_NORMALISED ? f->den : 1;
+    e = v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, idx_begin, idx_end, OUT_EDGES, nullptr, st, &E)
+                                       : launch_triangle_tiled(v->dev, idx_begin, idx_end, OUT_EDGES, nullptr, st, &E);
+    if (e != hipSuccess) return dev_fail(e, "launching the edge kernels");
     return ok();
 }
 

@@ -69,6 +69,14 @@ RowImage make_rows(const std::vector<std::pair<int, std::pair<const uint8_t *, i
 // The whole dictionary as a column set.
 ColSet full_colset(const DevVocab &D);
 
+// Arguments of the triangle calls (nw_all_pairs_scores and its forms): NW_OK
+// or the error already recorded.
+int check_triangle_args(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, const void *d_out);
+// Enqueue the triangle of pair indices [idx_begin, idx_end) on the kernel the
+// dictionary needs (register-row, or anti-diagonal for words past kMaxLen).
+hipError_t launch_triangle(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt, void *d_out,
+                           hipStream_t stream);
+
 // Key origin of a query batch whose longest query has qmax symbols; -1 when
 // its scores could leave int16.
 long query_lo(const nw_vocab *v, uint32_t qmax);

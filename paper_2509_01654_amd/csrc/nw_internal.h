@@ -68,19 +68,37 @@ struct DevVocab {
     int32_t lo, hi;             // score bounds
 };
 
-enum OutKind { OUT_I8 = 1, OUT_I16 = 2 };
+enum OutKind { OUT_I8 = 1, OUT_I16 = 2, OUT_EDGES = 3 };
+
+// Sink of the threshold edge emitter (graph export, Section 5): every pair
+// (i, j), i < j, whose raw score s or normalised weight 100 s / max(len i,
+// len j) lies in the closed slice is appended as (i, j, s).  The slice is
+// [lo, hi] on s when normalised == 0, and [lo/den, hi/den] on the weight
+// otherwise, compared exactly in integers: lo*m <= 100*s*den <= hi*m with
+// m = max(len i, len j, 1).  `count` counts every passing pair; only the
+// first `cap` appended are stored, in no particular order.
+struct EdgeSink {
+    int32_t *ei;
+    int32_t *ej;
+    int16_t *es;
+    unsigned long long *count;
+    uint64_t cap;
+    int32_t normalised;
+    int32_t lo, hi, den;
+};
 
 // Launchers.  Each enqueues on `stream` and returns the hipError_t of the
 // launches.
 
-// Triangle scores of pair indices [idx_begin, idx_end).
+// Triangle scores of pair indices [idx_begin, idx_end); with out_kind ==
+// OUT_EDGES the pairs of that range go to the edge sink E instead of d_out.
 hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
-                                 void *d_out, hipStream_t stream);
+                                 void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
                                  void *d_out, hipStream_t stream);
 // Anti-diagonal (16 lanes per pair) kernel, words up to 256 symbols.
 hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
-                                void *d_out, hipStream_t stream);
+                                void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
 
 // Per-row top-k lists of the rows R (pairs grouped by length, h_off = host
 // copy of R.off) against the column set C, split over nsplit column ranges:

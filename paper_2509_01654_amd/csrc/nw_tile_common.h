@@ -24,6 +24,22 @@ __device__ __forceinline__ void decode_block_pair(uint32_t t, uint32_t &r, uint3
     r = t - bb * (bb + 1) / 2;
 }
 
+// The block pair of this workgroup.  rbn == 0: column-major over all pairs
+// r <= b (decode_block_pair).  rbn > 0: row-major over block rows rb0 ..
+// rb0+rbn-1 and every column block, grid rbn*nb; returns false for b < r
+// (no such tile).  The window keeps launches for a narrow pair-index range
+// from spanning the whole triangle.
+__device__ __forceinline__ bool tile_block_pair(uint32_t rb0, uint32_t rbn, int nb, uint32_t &r, uint32_t &b)
+{
+    if (rbn == 0) {
+        decode_block_pair(blockIdx.x, r, b);
+        return true;
+    }
+    r = rb0 + blockIdx.x / (uint32_t)nb;
+    b = blockIdx.x % (uint32_t)nb;
+    return b >= r;
+}
+
 // Dwords per profile row: LA rounded up to whole 16-byte reads, then to an
 // odd number of 16-byte units.  Lanes read the rows of different symbols at
 // the same offset in one ds_read_b128; with an odd row stride two rows share
@@ -130,6 +146,76 @@ __device__ __forceinline__ void pair_scores(const uint8_t *lane_word, int lb, in
         const int off = gap * (LA + lb);
         s0 = (int)g[0] + off;
         s1 = (int)g[1] + off;
+    }
+}
+
+// Does the pair with raw score s and word lengths la, lb pass the slice of E?
+__device__ __forceinline__ bool edge_passes(const EdgeSink &E, int s, int la, int lb)
+{
+    if (!E.normalised) return s >= E.lo && s <= E.hi;
+    const int64_t m = max(max(la, lb), 1);
+    const int64_t w = 100ll * (int64_t)s * (int64_t)E.den;
+    return w >= (int64_t)E.lo * m && w <= (int64_t)E.hi * m;
+}
+
+// Store the staged scores of row word u (caller index, length la) against
+// the columns jstart .. J1-1, srow[t] = score(u, jstart + t), restricted to
+// pair indices in [idx_begin, idx_end): as triangle entries out[idx -
+// idx_begin] (int8 / int16), or as edges into E (OUT_EDGES).  Edges take one
+// atomic per wavefront and row that has any: the wavefront counts its passing
+// pairs with ballots, reserves that many slots, then writes them in the same
+// order.  Every thread of the workgroup calls this with the same arguments.
+__device__ __forceinline__ void store_row(const DevVocab &V, int64_t u, int la, int64_t jstart, int64_t J1,
+                                          const int16_t *srow, uint64_t idx_begin, uint64_t idx_end, void *out,
+                                          int out_kind, const EdgeSink &E)
+{
+    const uint64_t base = row_start_idx(V.n, u) + (uint64_t)(jstart - u - 1);
+    const int64_t len = J1 - jstart;
+    const int tid = threadIdx.x;
+    if (out_kind != OUT_EDGES) {
+        for (int64_t t = tid; t < len; t += kThreads) {
+            const uint64_t idx = base + (uint64_t)t;
+            if (idx >= idx_begin && idx < idx_end) {
+                const int16_t s = srow[t];
+                if (out_kind == OUT_I8)
+                    static_cast<int8_t *>(out)[idx - idx_begin] = (int8_t)s;
+                else
+                    static_cast<int16_t *>(out)[idx - idx_begin] = s;
+            }
+        }
+        return;
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    auto passes = [&](int64_t t) {
+        if (t >= len) return false;
+        const uint64_t idx = base + (uint64_t)t;
+        return idx >= idx_begin && idx < idx_end && edge_passes(E, srow[t], la, V.clen[jstart + t]);
+    };
+    // the trip count is uniform over the wavefront, so every ballot sees all 64 lanes
+    uint32_t cnt = 0;
+    for (int64_t t0 = (int64_t)wave * 64; t0 < len; t0 += kThreads) cnt += (uint32_t)__popcll(__ballot(passes(t0 + lane)));
+    if (cnt == 0) return;
+    uint32_t plo = 0, phi = 0;
+    if (lane == 0) {
+        const unsigned long long p = atomicAdd(E.count, (unsigned long long)cnt);
+        plo = (uint32_t)p;
+        phi = (uint32_t)(p >> 32);
+    }
+    uint64_t pos = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)plo) |
+                   ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)phi) << 32);
+    for (int64_t t0 = (int64_t)wave * 64; t0 < len; t0 += kThreads) {
+        const int64_t t = t0 + lane;
+        const bool p = passes(t);
+        const uint64_t m = __ballot(p);
+        if (p) {
+            const uint64_t q = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (q < E.cap) {
+                E.ei[q] = (int32_t)u;
+                E.ej[q] = (int32_t)(jstart + t);
+                E.es[q] = srow[t];
+            }
+        }
+        pos += (uint64_t)__popcll(m);
     }
 }
 

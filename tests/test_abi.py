@@ -81,3 +81,30 @@ def test_load_vocab_rejects_bad_input_before_any_device_call():
     # misaligned device memory
     rc, _ = _load(ok_syms, ok_offs, pm, d_mem=(1 << 20) + 8)
     assert rc == nw.NW_EINVAL
+
+
+def test_graph_and_export_arguments_rejected_on_the_host():
+    """Argument checks that fail before any device call (fake non-NULL pointers
+    are never dereferenced on these paths)."""
+    lib = nw.load_library()
+    need = ctypes.c_uint64()
+    assert lib.nw_graph_workspace_bytes(1000, ctypes.byref(need)) == nw.NW_OK and need.value > 8 * 1000
+    assert lib.nw_graph_workspace_bytes(1 << 31, ctypes.byref(need)) == nw.NW_EINVAL
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.nw_graph_csr(1 << 31, fake, fake, 1, fake, fake, fake, 1 << 30, None) == nw.NW_EINVAL
+    assert lib.nw_graph_csr(10, None, None, 1, fake, fake, fake, 1 << 30, None) == nw.NW_EINVAL
+    assert lib.nw_graph_csr(10, fake, fake, 1, fake, fake, ctypes.c_void_p((1 << 20) + 8), 1 << 30,
+                            None) == nw.NW_EINVAL
+    assert lib.nw_graph_csr(10, fake, fake, 1, fake, fake, fake, 8, None) == nw.NW_ENOMEM
+    seeds = np.array([3, 10], np.int32)
+    assert lib.nw_ego_network(10, fake, fake, seeds.ctypes.data, 2, 3, fake, None) == nw.NW_EINVAL
+    assert "seed 10" in lib.nw_last_error().decode()
+    seeds = np.array([-1], np.int32)
+    assert lib.nw_ego_network(10, fake, fake, seeds.ctypes.data, 1, 3, fake, None) == nw.NW_EINVAL
+    assert lib.nw_ego_network(10, fake, fake, None, 1, 3, fake, None) == nw.NW_EINVAL
+    assert lib.nw_ego_network(10, fake, fake, None, 0, 2_000_000, fake, None) == nw.NW_EINVAL
+    # export and edges: a NULL dictionary is refused first
+    assert lib.nw_export_triangle(None, 0, 1, nw.NW_I8, 1, fake, fake, nw._CHUNK_FN(lambda *a: 0), None,
+                                  None) == nw.NW_EINVAL
+    f = nw._EdgeFilter(0, 0, 1, 1)
+    assert lib.nw_all_pairs_edges(None, 0, 1, ctypes.byref(f), fake, fake, fake, 1, fake, None) == nw.NW_EINVAL
