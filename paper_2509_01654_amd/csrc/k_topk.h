@@ -94,7 +94,11 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
     }
     const ProfileRole role = profile_role(tid, V.alphabet);
     const int CPL = V.CB / kThreads;
-    const int lane_base = wave * 64 * CPL + lane;   // this lane's first slot in the block
+    // Column word c of this lane is slot c*256 + wave*64 + lane: each wavefront
+    // takes every fourth group of 64 consecutive (length-sorted) slots, so the
+    // four wavefronts get the same mix of lengths and reach the per-row-pair
+    // barrier together, while each group's lanes still have near-equal lengths.
+    const int lane_base = wave * 64 + lane;
 
     for (uint32_t k = pbeg; k < pend; ++k) {
         const int32_t a0 = V.rpairs[2 * k], a1 = V.rpairs[2 * k + 1];
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
         // One column word of this lane: its DP against the row pair, then the
         // histogram and both endpoints' candidate tests.
         auto column = [&](const uint32_t(&bw)[kWordBytes / 4], int c) __attribute__((always_inline)) {
-            const uint2 m = meta[lane_base + c * 64];
+            const uint2 m = meta[lane_base + c * kThreads];
             const int lb = (int)(m.x >> 16);
             const int col = (int)(m.x & 0xFFFF);
             const int ts_j = (int)m.y;
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
         // copied between registers; the fetch past the last word re-reads the
         // last one.
         const uint8_t *wbase = V.bsym + (J0 + lane_base) * kWordBytes;
-        auto word_at = [&](int c) { return wbase + (int64_t)min(c, CPL - 1) * 64 * kWordBytes; };
+        auto word_at = [&](int c) { return wbase + (int64_t)min(c, CPL - 1) * kThreads * kWordBytes; };
         uint32_t bwA[kWordBytes / 4], bwB[kWordBytes / 4];
         load_word(bwA, word_at(0));
         for (int c = 0; c < CPL; c += 2) {

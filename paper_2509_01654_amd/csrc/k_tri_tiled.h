@@ -77,7 +77,9 @@ __device__ __forceinline__ void tri_tile(const DevVocab &V, uint32_t r, uint32_t
             const int32_t su2 = V.rpairs[2 * k + 1];
             int16_t *sdst = stg + (size_t)(k % 3) * 2 * CB;
             for (int c = 0; c < CPL; ++c) {
-                const int64_t slot = J0 + (int64_t)(wave * 64 * CPL + c * 64 + lane);
+                // groups of 64 length-sorted slots dealt round-robin to the
+                // wavefronts, so all four carry the same mix of lengths
+                const int64_t slot = J0 + (int64_t)(c * kThreads + wave * 64 + lane);
                 const int lb = V.blen[slot];
                 const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);
                 int s0, s1;
