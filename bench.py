@@ -426,6 +426,7 @@ def main():
                          "n_words": dv.n, "k": k, "pairs": E, "cells": cells}
         rec["phase_ms"] = {"threshold_prepass": round(pre, 3), "main_pass": round(main_ms, 3),
                            "select": round(sel, 3)}
+        rec["overflow_words"] = dv.topk_overflow_words()
         achieved = OPS_PER_CELL * cells / (main_ms / 1e3)
         tr = counter_traffic()
         rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),

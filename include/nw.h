@@ -222,6 +222,11 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
  * (milliseconds; any pointer may be NULL). */
 int nw_topk_phase_times(const nw_vocab *v, float *prepass_ms, float *main_ms, float *select_ms);
 
+/* Number of words whose candidate list overflowed in the last completed
+ * nw_all_pairs_topk call on this dictionary and were recomputed exactly
+ * (their lists are exact either way). */
+int nw_topk_overflow_words(const nw_vocab *v, uint32_t *words);
+
 /* Workspace bytes nw_query needs for n_q query words (q_symbols is unused). */
 int nw_query_workspace_bytes(const nw_vocab *v, uint64_t n_q, uint64_t q_symbols, uint32_t k, uint64_t *bytes);
 

@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
         "nw_topk_phase_times": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                                ctypes.POINTER(ctypes.c_float)]),
         "nw_query": (ctypes.c_int, [P, P, P, u64, u32, P, P, P, u64, P]),
+        "nw_topk_overflow_words": (ctypes.c_int, [P, ctypes.POINTER(u32)]),
         "nw_all_pairs_edges": (ctypes.c_int, [P, u64, u64, ctypes.POINTER(_EdgeFilter), P, P, P, u64, P, P]),
         "nw_export_triangle": (ctypes.c_int, [P, u64, u64, ctypes.c_int, u64, P, P, _CHUNK_FN, P, P]),
         "nw_graph_workspace_bytes": (ctypes.c_int, [u64, ctypes.POINTER(u64)]),
@@ -320,6 +321,12 @@ class Vocab:
         return i[:m], j[:m], sc[:m], count
 
     # ------------------------------------------------------------------ top-k
+    def topk_overflow_words(self) -> int:
+        """Words of the last all_pairs_topk call that were recomputed exactly."""
+        out = ctypes.c_uint32()
+        _check(_lib.nw_topk_overflow_words(self._h, ctypes.byref(out)))
+        return out.value
+
     def topk_workspace_bytes(self, k: int) -> int:
         out = ctypes.c_uint64()
         _check(_lib.nw_topk_workspace_bytes(self._h, k, ctypes.byref(out)))

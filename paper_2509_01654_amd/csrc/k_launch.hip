@@ -246,6 +246,35 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
     return hipSuccess;
 }
 
+__global__ void k_scatter_lists(const int16_t *qs, const int32_t *qi, const int32_t *words, uint32_t B, int kq, int k,
+                                int16_t *score, int32_t *index)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B) return;
+    const int32_t w = words[t];
+    int o = 0;
+    for (int c = 0; c < kq && o < k; ++c) {
+        const int32_t j = qi[(size_t)t * kq + c];
+        if (j == w) continue;   // no self-loops
+        score[(size_t)w * k + o] = qs[(size_t)t * kq + c];
+        index[(size_t)w * k + o] = j;
+        ++o;
+    }
+    for (; o < k; ++o) {
+        score[(size_t)w * k + o] = (int16_t)-32768;
+        index[(size_t)w * k + o] = -1;
+    }
+}
+
+hipError_t launch_scatter_lists(const int16_t *qs, const int32_t *qi, const int32_t *words, uint32_t B, int kq, int k,
+                                int16_t *score, int32_t *index, hipStream_t stream)
+{
+    if (B == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_lists, dim3((B + 255) / 256), dim3(256), 0, stream, qs, qi, words, B, kq, k, score,
+                       index);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_reset_counters, dim3((n + 63) / 64), dim3(64), 0, stream, counters, n);

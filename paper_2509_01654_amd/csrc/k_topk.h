@@ -34,6 +34,9 @@ struct TopkArgs {
 // The LDS histogram is kept in kHistCopies copies (copy = lane mod
 // kHistCopies) so that lanes adding to the same popular bin in one
 // instruction mostly hit different addresses; the copies are summed at the end.
+#ifndef NW_TOPK_OCC6_MAX_LA
+#define NW_TOPK_OCC6_MAX_LA 10
+#endif
 constexpr int kHistCopies = 16;
 constexpr int kLdsHistMax = 1024;
 
@@ -55,8 +58,16 @@ __device__ __forceinline__ void emit_candidate(const TopkArgs &T, int64_t w, uin
     if (p < T.cap) T.lists[w * (int64_t)T.cap + p] = key;
 }
 
+// Waves per SIMD the main pass asks the compiler for: short rows fit six
+// waves in registers (the LDS holds six workgroups per CU) once the compiler
+// is asked; longer rows keep the compiler's own allocation (a tighter limit
+// would spill the DP column).
 template <int LA>
-__global__ __launch_bounds__(kThreads) void k_topk_tiled(DevVocab V, TopkArgs T)
+constexpr int topk_min_waves() { return LA <= NW_TOPK_OCC6_MAX_LA ? 6 : 1; }
+
+template <int LA>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(topk_min_waves<LA>())))
+void k_topk_tiled(DevVocab V, TopkArgs T)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t r, b;

@@ -57,8 +57,11 @@ int choose_block(uint64_t n)
 
 
 // Probe subset of the top-k threshold pre-pass.
-constexpr uint64_t kMaxProbes = 16384;
+constexpr uint64_t kMaxProbes = 8192;
 uint64_t num_probes(uint64_t n) { return n < kMaxProbes ? n : kMaxProbes; }
+// The first phase of the top-k main pass takes the block pairs (r, b) with
+// (b - r) mod kPhasePeriod == 0.
+constexpr int kPhasePeriod = 8;
 
 // Byte offsets of every region inside d_mem.
 struct Layout {
@@ -125,12 +128,23 @@ struct TopkWs {
 
 uint32_t topk_cap(uint64_t n, uint32_t k)
 {
-    // Expected candidates per word: the threshold is the (k+1)-th best key
-    // over M probe words, which ranks about (k+1)(n-1)/M among all n-1
-    // partners.  Twice that, plus a margin, bounds the list in practice; a
-    // word past the capacity is recomputed exactly.
+    // Expected candidates of one word.  The probe threshold is the (k+1)-th
+    // best key over M probe words and ranks about all = (k+1)(n-1)/M among
+    // the n-1 partners.  The first phase meets the share f of the partners in
+    // the block columns of its period and appends about f * all of them.  A
+    // word with at least k has its threshold raised to their k-th best, which
+    // ranks about k/f overall, and the second phase appends fewer than that;
+    // otherwise the probe threshold stays and it appends up to `all`.  Twice
+    // the sum, plus a margin, bounds the list in practice; a word past the
+    // capacity is recomputed exactly.
     const uint64_t M = num_probes(n);
-    double mean = M >= n ? (double)(k + 1) : (double)(k + 1) * (double)(n - 1) / (double)M;
+    const uint64_t CB = (uint64_t)choose_block(n);
+    const uint64_t nb = std::max<uint64_t>(1, (n + CB - 1) / CB);
+    const double f = std::min(1.0, (double)((nb + kPhasePeriod - 1) / kPhasePeriod) / (double)nb);
+    const double all = M >= n ? (double)(k + 1) : (double)(k + 1) * (double)(n - 1) / (double)M;
+    const double first = f * all;
+    const double second = first >= 2.0 * k ? (double)k / f : all;
+    const double mean = first + second;
     uint64_t cap = (uint64_t)(2.0 * mean) + 64;
     cap = (cap + 63) / 64 * 64;
     const uint64_t most = (n + 63) / 64 * 64;
@@ -668,14 +682,14 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     T.hist = reinterpret_cast<unsigned long long *>(d_hist);
     T.lo = D.lo;
     T.nbins = nbins;
-    T.phase_mod = 8;
+    T.phase_mod = kPhasePeriod;
     T.phase_lo = 0;
     T.phase_hi = 0;
     if ((e = launch_topk_main(D, T, st)) != hipSuccess) return dev_fail(e, "launching the top-k main pass");
     if ((e = launch_tighten(cnt, lists, W.cap, (int64_t)n, (int)k, thr, st)) != hipSuccess)
         return dev_fail(e, "launching the threshold update");
     T.phase_lo = 1;
-    T.phase_hi = 7;
+    T.phase_hi = kPhasePeriod - 1;
     if ((e = launch_topk_main(D, T, st)) != hipSuccess) return dev_fail(e, "launching the top-k main pass");
     if ((e = hipEventRecord(vm->ev[2], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 3. the best k of each word's candidates
@@ -686,65 +700,56 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     uint32_t novf = 0;
     if ((e = hipMemcpyAsync(&novf, ovf, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return dev_fail(e, "reading the overflow count");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail(e, "top-k");
+    vm->last_overflow = novf;
     for (int ph = 0; ph < 3; ++ph)
         if ((e = hipEventElapsedTime(&vm->phase_ms[ph], vm->ev[ph], vm->ev[ph + 1])) != hipSuccess)
             return dev_fail(e, "reading timing events");
     if (novf == 0) return ok();
     std::vector<int32_t> words(novf);
     if ((e = hipMemcpy(words.data(), ovf + 1, 4ull * novf, hipMemcpyDeviceToHost)) != hipSuccess) return dev_fail(e, "reading overflowed words");
-    // reuse the list area: rows (query image) then partial lists of k+1 keys
+    // Each overflowed word is a query of its own symbols against the whole
+    // dictionary (k+1 best, the word itself dropped).  The list area is free
+    // now; the words go through it in batches that fit.
     const int kq = (int)k + 1;
-    std::vector<std::pair<int, std::pair<const uint8_t *, int32_t>>> rows;
-    for (uint32_t t = 0; t < novf; ++t)
-        rows.push_back({v->h_clen[words[t]], {&v->h_csym[(size_t)words[t] * kWordBytes], (int32_t)t}});
-    RowImage img = make_rows(rows);
     const int nsplit = 16;
-    const uint64_t need = align_up(img.sym.size(), 256) + align_up(img.pairs.size() * 4 + 8, 256) +
-                          align_up((kMaxLen + 2) * 4, 256) + align_up(img.orig.size() * 4, 256) +
-                          (uint64_t)novf * nsplit * 4 * kq * 8 + (uint64_t)novf * kq * 6;
-    if (need > 8 * n * (uint64_t)W.cap) return fail(NW_ENOMEM, "overflow recomputation does not fit the workspace");
-    uint8_t *q = reinterpret_cast<uint8_t *>(lists);
-    uint8_t *qsym = q; q += align_up(img.sym.size(), 256);
-    int32_t *qpairs = reinterpret_cast<int32_t *>(q); q += align_up(img.pairs.size() * 4 + 8, 256);
-    uint32_t *qoff = reinterpret_cast<uint32_t *>(q); q += align_up((kMaxLen + 2) * 4, 256);
-    int32_t *qorig = reinterpret_cast<int32_t *>(q); q += align_up(img.orig.size() * 4, 256);
-    uint64_t *qpart = reinterpret_cast<uint64_t *>(q); q += (uint64_t)novf * nsplit * 4 * kq * 8;
-    int16_t *qs = reinterpret_cast<int16_t *>(q);
-    int32_t *qi = reinterpret_cast<int32_t *>(ws + W.partial);
-    if ((e = hipMemcpy(qsym, img.sym.data(), img.sym.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(qpairs, img.pairs.data(), img.pairs.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(qoff, img.off.data(), img.off.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(qorig, img.orig.data(), img.orig.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
-        return dev_fail(e, "uploading overflowed words");
-    RowSet QR;
-    QR.sym = qsym;
-    QR.pairs = qpairs;
-    QR.off = qoff;
-    QR.orig = qorig;
-    if ((e = launch_query(D, QR, img.off.data(), full_colset(D), kq, nsplit, qpart, st)) != hipSuccess ||
-        (e = launch_merge(qpart, nsplit * 4, kq, novf, kq, D.lo, qs, qi, nullptr, 1, st)) != hipSuccess)
-        return dev_fail(e, "launching the overflow recomputation");
-    std::vector<int16_t> hs((size_t)novf * kq);
-    std::vector<int32_t> hi((size_t)novf * kq);
-    if ((e = hipMemcpyAsync(hs.data(), qs, hs.size() * 2, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(hi.data(), qi, hi.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
-        return dev_fail(e, "reading the overflow recomputation");
-    std::vector<int16_t> rs(k);
-    std::vector<int32_t> ri(k);
-    for (uint32_t t = 0; t < novf; ++t) {
-        const int32_t w = words[t];
-        uint32_t o = 0;
-        for (int c = 0; c < kq && o < k; ++c) {
-            if (hi[(size_t)t * kq + c] == w) continue;   // no self-loops
-            rs[o] = hs[(size_t)t * kq + c];
-            ri[o] = hi[(size_t)t * kq + c];
-            ++o;
+    const uint64_t area = 8 * n * (uint64_t)W.cap;
+    const uint64_t fixed = align_up((kMaxLen + 2) * 4, 256) + 8 * 256;
+    const uint64_t per_word = kWordBytes + 8 + 4 + 4 + (uint64_t)nsplit * 4 * kq * 8 + (uint64_t)kq * 6;
+    const uint64_t batch = area > fixed ? (area - fixed) / per_word : 0;
+    if (batch == 0) return fail(NW_ENOMEM, "the candidate lists are too small to recompute an overflowed word");
+    for (uint64_t t0 = 0; t0 < novf; t0 += batch) {
+        const uint32_t B = (uint32_t)std::min<uint64_t>(batch, novf - t0);
+        std::vector<std::pair<int, std::pair<const uint8_t *, int32_t>>> rows;
+        for (uint32_t t = 0; t < B; ++t) {
+            const int32_t w = words[t0 + t];
+            rows.push_back({v->h_clen[w], {&v->h_csym[(size_t)w * kWordBytes], (int32_t)t}});
         }
-        for (; o < k; ++o) { rs[o] = -32768; ri[o] = -1; }
-        if ((e = hipMemcpy(d_score + (size_t)w * k, rs.data(), 2ull * k, hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(d_index + (size_t)w * k, ri.data(), 4ull * k, hipMemcpyHostToDevice)) != hipSuccess)
-            return dev_fail(e, "writing the overflow recomputation");
+        RowImage img = make_rows(rows);
+        uint8_t *q = reinterpret_cast<uint8_t *>(lists);
+        uint8_t *qsym = q; q += align_up(img.sym.size(), 256);
+        int32_t *qpairs = reinterpret_cast<int32_t *>(q); q += align_up(img.pairs.size() * 4 + 8, 256);
+        uint32_t *qoff = reinterpret_cast<uint32_t *>(q); q += align_up((kMaxLen + 2) * 4, 256);
+        int32_t *qorig = reinterpret_cast<int32_t *>(q); q += align_up(img.orig.size() * 4, 256);
+        int32_t *qwords = reinterpret_cast<int32_t *>(q); q += align_up(4ull * B, 256);
+        uint64_t *qpart = reinterpret_cast<uint64_t *>(q); q += align_up((uint64_t)B * nsplit * 4 * kq * 8, 256);
+        int32_t *qi = reinterpret_cast<int32_t *>(q); q += align_up((uint64_t)B * kq * 4, 256);
+        int16_t *qs = reinterpret_cast<int16_t *>(q);
+        if ((e = hipMemcpy(qsym, img.sym.data(), img.sym.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(qpairs, img.pairs.data(), img.pairs.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(qoff, img.off.data(), img.off.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(qorig, img.orig.data(), img.orig.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(qwords, words.data() + t0, 4ull * B, hipMemcpyHostToDevice)) != hipSuccess)
+            return dev_fail(e, "uploading overflowed words");
+        RowSet QR;
+        QR.sym = qsym;
+        QR.pairs = qpairs;
+        QR.off = qoff;
+        QR.orig = qorig;
+        if ((e = launch_query(D, QR, img.off.data(), full_colset(D), kq, nsplit, qpart, st)) != hipSuccess ||
+            (e = launch_merge(qpart, nsplit * 4, kq, B, kq, D.lo, qs, qi, nullptr, 1, st)) != hipSuccess ||
+            (e = launch_scatter_lists(qs, qi, qwords, B, kq, (int)k, d_score, d_index, st)) != hipSuccess)
+            return dev_fail(e, "launching the overflow recomputation");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail(e, "recomputing overflowed words");
     }
     return ok();
 }
@@ -755,6 +760,13 @@ int nw_topk_phase_times(const nw_vocab *v, float *prepass_ms, float *main_ms, fl
     if (prepass_ms) *prepass_ms = v->phase_ms[0];
     if (main_ms) *main_ms = v->phase_ms[1];
     if (select_ms) *select_ms = v->phase_ms[2];
+    return ok();
+}
+
+int nw_topk_overflow_words(const nw_vocab *v, uint32_t *words)
+{
+    if (!v || !words) return fail(NW_EINVAL, "NULL argument");
+    *words = v->last_overflow;
     return ok();
 }
 

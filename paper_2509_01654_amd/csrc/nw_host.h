@@ -23,6 +23,7 @@ struct nw_vocab {
     // phase timing of the last top-k call (HIP events on the caller's stream)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float phase_ms[3] = {0, 0, 0};
+    uint32_t last_overflow = 0;       // words recomputed exactly by the last top-k call
     ~nw_vocab()
     {
         for (auto &e : ev)

@@ -111,6 +111,12 @@ hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_of
 hipError_t launch_merge(const uint64_t *partial, int P, int kin, int64_t rows, int kout, int lo, int16_t *score,
                         int32_t *index, uint64_t *thr, int rank, hipStream_t stream);
 
+// Write recomputed lists: for t < B, the first k entries of (qs, qi)[t][0..kq)
+// whose index is not words[t] go to score/index[words[t]][0..k), padded with
+// (INT16_MIN, -1).
+hipError_t launch_scatter_lists(const int16_t *qs, const int32_t *qi, const int32_t *words, uint32_t B, int kq, int k,
+                                int16_t *score, int32_t *index, hipStream_t stream);
+
 // Main pass of the all-pairs top-k: candidates >= thr into per-word lists,
 // plus the histogram.
 struct TopkArgs;

@@ -103,6 +103,7 @@ def test_overflow_recomputation(monkeypatch):
     monkeypatch.setenv("NW_TOPK_CAP", "40")
     v = synth.zipf_vocab(17000, seed=23, mean_len=4.0, max_len=12)
     dv, s, i, h = _gpu_topk(v, 32)
+    assert dv.topk_overflow_words() > 1000   # most words overflow a 40-key list
     rows = np.unique(np.concatenate([np.arange(0, 30), np.random.default_rng(2).integers(0, v.n, 100)]))
     for r in rows:
         ws, wi, _ = oracle.topk_rows(v.symbols, v.offsets, _sim(v), -1, 32, r0=int(r), r1=int(r) + 1)
