@@ -45,17 +45,61 @@ __host__ __device__ constexpr uint32_t topk_hist_bytes(int nbins)
 {
     return nbins <= kLdsHistMax ? 4u * kHistCopies * hist_stride(nbins) : 0u;
 }
-// LDS: two profile buffers, the histogram copies, and the column block's
-// per-slot metadata (length, column, threshold score; 8 bytes per slot).
+// Candidates are first appended to one of two LDS pools (by row-pair parity)
+// and moved to the global lists between row pairs, many at a time, so the DP
+// loop never waits on a global atomic.  A pool that is full sends further
+// candidates straight to the global lists.
+constexpr int kPool = 96;          // entries per pool
+constexpr int kPoolFlush = 48;     // a pool is flushed once it holds this many
+
+// LDS: two profile buffers, the histogram copies, the column block's per-slot
+// metadata (length, column, threshold score; 8 bytes per slot), and the two
+// candidate pools (keys, words, counters).
+__host__ __device__ constexpr uint32_t topk_pool_bytes() { return 2u * kPool * 12u + 16u; }
 __host__ __device__ constexpr uint32_t topk_lds_bytes(int LA, int alphabet, int nbins, int CB)
 {
-    return 2u * profile_bytes(LA, alphabet) + topk_hist_bytes(nbins) + 8u * (uint32_t)CB;
+    return 2u * profile_bytes(LA, alphabet) + topk_hist_bytes(nbins) + 8u * (uint32_t)CB + topk_pool_bytes();
 }
 
 __device__ __forceinline__ void emit_candidate(const TopkArgs &T, int64_t w, uint64_t key)
 {
     const uint32_t p = atomicAdd(&T.cnt[w], 1u);
     if (p < T.cap) T.lists[w * (int64_t)T.cap + p] = key;
+}
+
+// The LDS candidate pools of one workgroup.
+struct CandPool {
+    uint64_t *key;    // [2][kPool]
+    int32_t *word;    // [2][kPool]
+    uint32_t *n;      // [2] appends so far (may pass kPool)
+};
+
+// Offer (w, key) through pool b; the key has passed the score test only, the
+// full key test against thr[w] happens when it is moved to the global list.
+__device__ __forceinline__ void pool_offer(const CandPool &P, int b, const TopkArgs &T, int64_t w, uint64_t key)
+{
+    const uint32_t p = atomicAdd(&P.n[b], 1u);
+    if (p < (uint32_t)kPool) {
+        P.key[b * kPool + p] = key;
+        P.word[b * kPool + p] = (int32_t)w;
+    } else if (key >= T.thr[w]) {
+        emit_candidate(T, w, key);
+    }
+}
+
+// Move pool b to the global lists.  Every thread of the workgroup calls it
+// while no thread appends to pool b; ends with a barrier and the pool empty
+// (the reset is ordered before later appends by the caller's next barrier).
+__device__ __forceinline__ void pool_flush(const CandPool &P, int b, const TopkArgs &T, uint32_t count)
+{
+    const uint32_t m = min(count, (uint32_t)kPool);
+    for (uint32_t i = threadIdx.x; i < m; i += kThreads) {
+        const int32_t w = P.word[b * kPool + i];
+        const uint64_t key = P.key[b * kPool + i];
+        if (key >= T.thr[w]) emit_candidate(T, w, key);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) P.n[b] = 0;
 }
 
 // Waves per SIMD the main pass asks the compiler for: short rows fit six
@@ -96,6 +140,14 @@ void k_topk_tiled(DevVocab V, TopkArgs T)
     // metadata once -- x = column | length << 16, y = score of the column
     // word's threshold (a pair can only enter that word's list at or above it)
     uint2 *meta = reinterpret_cast<uint2 *>(lds + 2 * prof_bytes + topk_hist_bytes(T.nbins));
+    CandPool pool;
+    {
+        uint8_t *pb = lds + 2 * prof_bytes + topk_hist_bytes(T.nbins) + 8u * (uint32_t)CB;
+        pool.key = reinterpret_cast<uint64_t *>(pb);
+        pool.word = reinterpret_cast<int32_t *>(pb + 2 * kPool * 8);
+        pool.n = reinterpret_cast<uint32_t *>(pb + 2 * kPool * 12);
+        if (tid < 2) pool.n[tid] = 0;
+    }
     for (int i = tid; i < CB; i += kThreads) {
         const int64_t slot = J0 + i;
         const uint32_t col = V.bcol[slot];
@@ -117,6 +169,14 @@ void k_topk_tiled(DevVocab V, TopkArgs T)
         build_profile<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (k & 1) * prof_bytes),
                           V.bsym + (int64_t)a0 * kWordBytes, V.bsym + (int64_t)(a1 >= 0 ? a1 : a0) * kWordBytes, role);
         __syncthreads();
+        // This row pair appends to pool pb; the other pool took the previous
+        // row pair's candidates, which every wavefront has finished (barrier
+        // above), so its count is the same for all threads.
+        const int pb = (int)(k & 1);
+        {
+            const uint32_t other = pool.n[pb ^ 1];
+            if (other >= (uint32_t)kPoolFlush) pool_flush(pool, pb ^ 1, T, other);
+        }
         const int64_t u0 = I0 + V.bcol[a0];
         const int64_t u1 = a1 >= 0 ? I0 + V.bcol[a1] : -1;
         const uint64_t thr_u0 = T.thr[u0];
@@ -144,29 +204,23 @@ void k_topk_tiled(DevVocab V, TopkArgs T)
             // each unordered pair once: in a diagonal block only j > u
             const bool v0 = (r < b) || (j > u0);
             const bool v1 = u1 >= 0 && ((r < b) || (j > u1));
-            if (v0) {
-                if (lds_hist) atomicAdd(&hist[s0], 1u);
-                else if (T.hist) atomicAdd(&T.hist[s0 - T.lo], 1ull);
-                if (s0 >= ts_u0) {
-                    const uint64_t kr = nb_key(s0, T.lo, (uint32_t)j);
-                    if (kr >= thr_u0) emit_candidate(T, u0, kr);
-                }
-                if (s0 >= ts_j) {
-                    const uint64_t kc = nb_key(s0, T.lo, (uint32_t)u0);
-                    if (kc >= T.thr[j]) emit_candidate(T, j, kc);
-                }
+            if (lds_hist) {
+                if (v0) atomicAdd(&hist[s0], 1u);
+                if (v1) atomicAdd(&hist[s1], 1u);
+            } else if (T.hist) {
+                if (v0) atomicAdd(&T.hist[s0 - T.lo], 1ull);
+                if (v1) atomicAdd(&T.hist[s1 - T.lo], 1ull);
             }
-            if (v1) {
-                if (lds_hist) atomicAdd(&hist[s1], 1u);
-                else if (T.hist) atomicAdd(&T.hist[s1 - T.lo], 1ull);
-                if (s1 >= ts_u1) {
-                    const uint64_t kr = nb_key(s1, T.lo, (uint32_t)j);
-                    if (kr >= thr_u1) emit_candidate(T, u1, kr);
-                }
-                if (s1 >= ts_j) {
-                    const uint64_t kc = nb_key(s1, T.lo, (uint32_t)u1);
-                    if (kc >= T.thr[j]) emit_candidate(T, j, kc);
-                }
+            // A pair enters a list only at or above the owner's threshold
+            // score.  One test covers all four lists; the few lanes that pass
+            // it (about one pair in a thousand) take the detailed tests.
+            const bool c0 = v0 && s0 >= min(ts_u0, ts_j);
+            const bool c1 = v1 && s1 >= min(ts_u1, ts_j);
+            if (__builtin_expect(c0 || c1, 0)) {
+                if (c0 && s0 >= ts_u0) pool_offer(pool, pb, T, u0, nb_key(s0, T.lo, (uint32_t)j));
+                if (c0 && s0 >= ts_j) pool_offer(pool, pb, T, j, nb_key(s0, T.lo, (uint32_t)u0));
+                if (c1 && s1 >= ts_u1) pool_offer(pool, pb, T, u1, nb_key(s1, T.lo, (uint32_t)j));
+                if (c1 && s1 >= ts_j) pool_offer(pool, pb, T, j, nb_key(s1, T.lo, (uint32_t)u1));
             }
         };
         // Lane words are prefetched one ahead into two alternating register
@@ -184,6 +238,12 @@ void k_topk_tiled(DevVocab V, TopkArgs T)
             load_word(bwA, word_at(c + 2));
             column(bwB, c + 1);
         }
+    }
+    // the candidates still pooled
+    __syncthreads();
+    for (int b = 0; b < 2; ++b) {
+        const uint32_t left = pool.n[b];
+        if (left) pool_flush(pool, b, T, left);
     }
     if (lds_hist) {
         __syncthreads();
