@@ -434,7 +434,8 @@ class Server:
         return b.value, q.value
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        # at interpreter exit the module's library handle may already be gone
+        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
             _lib.nw_server_destroy(self._h)
             self._h = None
 
@@ -495,7 +496,8 @@ class Batch:
         return items.value, launches.value
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        # at interpreter exit the module's library handle may already be gone
+        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
             _lib.nw_batch_destroy(self._h)
             self._h = None
 

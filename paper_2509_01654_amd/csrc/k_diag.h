@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_
     constexpr int ROWS = kDiagLanes * R;
 
     uint32_t r, b;
-    if (!tile_block_pair(rb0, rbn, V.nb, r, b)) return;
+    if (!tile_block_pair(blockIdx.x, rb0, rbn, V.nb, r, b)) return;
     const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
     const uint32_t pbeg = rpo[0], pend = rpo[1];
     if (pbeg >= pend) return;

@@ -5,6 +5,8 @@
 // the row index, and one DP per thread with its scratch in shared memory (one
 // row of the score matrix instead of the whole matrix).
 #define NW_LAUNCH_TU 1
+#include <algorithm>
+
 #include "k_batch.h"
 #include "k_diag.h"
 #include "k_query.h"
@@ -113,21 +115,34 @@ static TriGrid tri_grid(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end)
     return {(uint32_t)all, 0, 0};
 }
 
-hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
-                                 hipStream_t stream, const EdgeSink *E)
+hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
+                                 int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E)
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
+    // a launch wants a few workgroups per slot (256 CUs x 6); tiles are split
+    // into runs of row pairs only when there are fewer tiles than that
+    constexpr uint64_t kTargetWorkgroups = 256 * 6 * 4;
+    constexpr uint32_t kMinRowPairs = 8;
     for (int LA = 0; LA <= V.lmax; ++LA) {
+        if (h_maxrp[LA] == 0) continue;   // no block has row pairs of this length
+        uint32_t chunks = 1;
+        if (G.blocks < kTargetWorkgroups) {
+            const uint32_t want = (uint32_t)((kTargetWorkgroups + G.blocks - 1) / G.blocks);
+            const uint32_t most = (h_maxrp[LA] + kMinRowPairs - 1) / kMinRowPairs;
+            chunks = std::max<uint32_t>(1, std::min(want, most));
+        }
+        uint32_t rpc = (h_maxrp[LA] + chunks - 1) / chunks;
         DevVocab Vc = V;
         uint64_t ib = idx_begin, ie = idx_end;
         void *po = d_out;
         int ok = out_kind;
         EdgeSink es = E ? *E : EdgeSink{};
         uint32_t rb0 = G.rb0, rbn = G.rbn;
-        void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn};
-        hipError_t e = launch_dyn(tab.tri[LA], dim3(G.blocks), tri_lds_bytes(LA, V.alphabet, V.CB), stream, args);
+        void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
+        hipError_t e = launch_dyn(tab.tri[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
+                                  tri_lds_bytes(LA, V.alphabet, V.CB), stream, args);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -172,7 +187,8 @@ hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t 
         uint32_t rb0 = G.rb0, rbn = G.rbn;
         hipError_t e;
         if (LA == 0) {
-            void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn};
+            uint32_t one = 1, all = 0xFFFFFFFFu;
+            void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &one, &all};
             e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
         } else {
             // rows per lane: the smallest class whose 16 lanes cover LA rows

@@ -95,15 +95,23 @@ __device__ __forceinline__ void tri_tile(const DevVocab &V, uint32_t r, uint32_t
 }
 
 
+// Workgroup = tile * chunks + chunk: a tile's row pairs of length LA are
+// split into `chunks` runs of at most rpc row pairs, so that launches over few
+// tiles (small dictionaries) still fill the GPU.
 template <int LA>
 __global__ __launch_bounds__(kThreads) void k_tri_tiled(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
-                                                        int out_kind, EdgeSink E, uint32_t rb0, uint32_t rbn)
+                                                        int out_kind, EdgeSink E, uint32_t rb0, uint32_t rbn,
+                                                        uint32_t chunks, uint32_t rpc)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t r, b;
-    if (!tile_block_pair(rb0, rbn, V.nb, r, b)) return;
+    if (!tile_block_pair(blockIdx.x / chunks, rb0, rbn, V.nb, r, b)) return;
     const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
-    tri_tile<LA>(V, r, b, rpo[0], rpo[1], idx_begin, idx_end, out, out_kind, E, lds);
+    const uint64_t pbeg64 = (uint64_t)rpo[0] + (uint64_t)(blockIdx.x % chunks) * rpc;
+    if (pbeg64 >= rpo[1]) return;
+    const uint32_t pbeg = (uint32_t)pbeg64;
+    const uint32_t pend = rpo[1] - pbeg <= rpc ? rpo[1] : pbeg + rpc;
+    tri_tile<LA>(V, r, b, pbeg, pend, idx_begin, idx_end, out, out_kind, E, lds);
 }
 
 }  // namespace nw

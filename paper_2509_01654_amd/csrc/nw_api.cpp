@@ -281,7 +281,7 @@ hipError_t nw::host::launch_triangle(const nw_vocab *v, uint64_t idx_begin, uint
     // words longer than the register-row limit take the anti-diagonal kernel
     const int kind = dt == NW_I8 ? OUT_I8 : OUT_I16;
     return v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, idx_begin, idx_end, kind, d_out, stream)
-                                          : launch_triangle_tiled(v->dev, idx_begin, idx_end, kind, d_out, stream);
+                                          : launch_triangle_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, kind, d_out, stream);
 }
 
 extern "C" {
@@ -502,6 +502,12 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     v->h_csym.assign(csym, csym + n * L.WB);
     v->h_clen.assign(clen, clen + n);
     v->h_rp_off.assign(rp_off, rp_off + (size_t)L.nb * (LM + 1) + 1);
+    v->h_maxrp.assign(LM + 1, 0);
+    for (uint64_t r = 0; r < L.nb; ++r)
+        for (uint32_t la = 0; la <= LM; ++la) {
+            const uint32_t c = rp_off[r * (LM + 1) + la + 1] - rp_off[r * (LM + 1) + la];
+            v->h_maxrp[la] = std::max(v->h_maxrp[la], c);
+        }
     v->smin = smin;
     v->smax = smax;
     v->n = n;
@@ -605,7 +611,7 @@ int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, 
     E.hi = f->hi;
     E.den = f->mode == NW_EDGE_NORMALISED ? f->den : 1;
     e = v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, idx_begin, idx_end, OUT_EDGES, nullptr, st, &E)
-                                       : launch_triangle_tiled(v->dev, idx_begin, idx_end, OUT_EDGES, nullptr, st, &E);
+                                       : launch_triangle_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, OUT_EDGES, nullptr, st, &E);
     if (e != hipSuccess) return dev_fail(e, "launching the edge kernels");
     return ok();
 }

@@ -92,8 +92,10 @@ struct EdgeSink {
 
 // Triangle scores of pair indices [idx_begin, idx_end); with out_kind ==
 // OUT_EDGES the pairs of that range go to the edge sink E instead of d_out.
-hipError_t launch_triangle_tiled(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
-                                 void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
+// h_maxrp[LA] (host) = most row pairs of length LA in one block: sets how
+// far tiles are split when the launch has few of them.
+hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
+                                 int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
                                  void *d_out, hipStream_t stream);
 // Anti-diagonal (16 lanes per pair) kernel, words up to 256 symbols.

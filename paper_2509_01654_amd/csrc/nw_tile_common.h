@@ -24,19 +24,19 @@ __device__ __forceinline__ void decode_block_pair(uint32_t t, uint32_t &r, uint3
     r = t - bb * (bb + 1) / 2;
 }
 
-// The block pair of this workgroup.  rbn == 0: column-major over all pairs
+// The block pair of tile t.  rbn == 0: column-major over all pairs
 // r <= b (decode_block_pair).  rbn > 0: row-major over block rows rb0 ..
 // rb0+rbn-1 and every column block, grid rbn*nb; returns false for b < r
 // (no such tile).  The window keeps launches for a narrow pair-index range
 // from spanning the whole triangle.
-__device__ __forceinline__ bool tile_block_pair(uint32_t rb0, uint32_t rbn, int nb, uint32_t &r, uint32_t &b)
+__device__ __forceinline__ bool tile_block_pair(uint32_t t, uint32_t rb0, uint32_t rbn, int nb, uint32_t &r, uint32_t &b)
 {
     if (rbn == 0) {
-        decode_block_pair(blockIdx.x, r, b);
+        decode_block_pair(t, r, b);
         return true;
     }
-    r = rb0 + blockIdx.x / (uint32_t)nb;
-    b = blockIdx.x % (uint32_t)nb;
+    r = rb0 + t / (uint32_t)nb;
+    b = t % (uint32_t)nb;
     return b >= r;
 }
 
