@@ -1,0 +1,24 @@
+"""bench.py's command line on the CPU: more than one GPU is refused with a
+message before any device work."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_traffic_gate_reads_the_counter_summary():
+    sys.path.insert(0, ROOT)
+    import bench
+    sha = bench.main_pass_sources_sha256()
+    assert len(sha) == 64
+    t = bench.counter_traffic()
+    # either the summary matches the current kernel sources, or the figure is withheld
+    assert t is None or (t[0] > 0 and t[1] > 0)
