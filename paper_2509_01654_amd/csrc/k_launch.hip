@@ -121,16 +121,18 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
-    // a launch wants a few workgroups per slot (256 CUs x 6); tiles are split
-    // into runs of row pairs only when there are fewer tiles than that
+    // A launch with fewer tiles than workgroup slots (256 CUs x 6) splits its
+    // tiles into runs of at least kMinRowPairs row pairs, up to about four
+    // workgroups per slot; short runs cost more than they balance.
     constexpr uint64_t kTargetWorkgroups = 256 * 6 * 4;
+    constexpr uint64_t kSplitBelow = 2048;
     constexpr uint32_t kMinRowPairs = 8;
     for (int LA = 0; LA <= V.lmax; ++LA) {
         if (h_maxrp[LA] == 0) continue;   // no block has row pairs of this length
         uint32_t chunks = 1;
-        if (G.blocks < kTargetWorkgroups) {
+        if (G.blocks < kSplitBelow) {
             const uint32_t want = (uint32_t)((kTargetWorkgroups + G.blocks - 1) / G.blocks);
-            const uint32_t most = (h_maxrp[LA] + kMinRowPairs - 1) / kMinRowPairs;
+            const uint32_t most = h_maxrp[LA] / kMinRowPairs;
             chunks = std::max<uint32_t>(1, std::min(want, most));
         }
         uint32_t rpc = (h_maxrp[LA] + chunks - 1) / chunks;
