@@ -49,22 +49,43 @@ def main_pass_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def counter_traffic():
-    """(bytes fetched, bytes written) per main pass from the counter summary, or
-    None when there is none or the kernel sources changed since it was taken."""
+def _summary_fields(prefix):
     try:
         text = open(COUNTER_SUMMARY, encoding="utf-8").read()
     except OSError:
-        return None
+        return {}
     fields = {}
     for line in text.splitlines():
-        if line.startswith("traffic:"):
-            for kv in line[len("traffic:"):].split():
+        if line.startswith(prefix):
+            for kv in line[len(prefix):].split():
                 k, _, val = kv.partition("=")
                 fields[k] = val
+    return fields
+
+
+def counter_traffic():
+    """(bytes fetched, bytes written) per main pass from the counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    fields = _summary_fields("traffic:")
     if fields.get("sources_sha256") != main_pass_sources_sha256():
         return None
     return float(fields["fetch_bytes"]), float(fields["write_bytes"])
+
+
+def counter_issue():
+    """VALU and LDS figures of the main pass from the same summary (same gate)."""
+    fields = _summary_fields("counters:")
+    if fields.pop("sources_sha256", None) != main_pass_sources_sha256():
+        return None
+    return {k: float(v) for k, v in fields.items()}
+
+
+# The paper's own GPU timings (a GTX 1060, i8 output, the device-to-host copy
+# included): context for the numbers here, not a baseline of this metric.
+PAPER_CONTEXT = {"gpu": "NVIDIA GTX 1060 6 GB (paper, Section 5)",
+                 "runs": [{"words": 20000, "ms": 484, "pairs_per_s": 4.1e8},
+                          {"words": 107000, "s": 21.3, "pairs_per_s": 2.7e8}],
+                 "note": "i8 triangle incl. D2H copy; no GCUPS, top-k, batched or served numbers are published"}
 
 
 def host_cpu_model() -> str:
@@ -326,7 +347,7 @@ def main():
     ap.add_argument("--workload", choices=["paper", "mid", "batched", "diag", "edges", "export"], default="paper")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-rates", default="10000,50000",
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000",
                     help="offered query rates (q/s) for the served form; empty to skip")
     ap.add_argument("--serve-queries", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -427,6 +448,7 @@ def main():
         rec["phase_ms"] = {"threshold_prepass": round(pre, 3), "main_pass": round(main_ms, 3),
                            "select": round(sel, 3)}
         rec["overflow_words"] = dv.topk_overflow_words()
+        rec["paper_context"] = PAPER_CONTEXT
         achieved = OPS_PER_CELL * cells / (main_ms / 1e3)
         tr = counter_traffic()
         rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
@@ -434,6 +456,9 @@ def main():
                            "traffic": None if tr is None else round(tr[0] + tr[1]),
                            "kernel": "k_topk_tiled (all-pairs main pass, every LA)",
                            "issue_frac": round(cells / (main_ms / 1e3) / PEAK_ISSUE_CELLS, 4)}
+        iss = counter_issue()
+        if iss is not None:
+            rec["roofline"]["counters"] = iss
         if tr is not None:
             rec["roofline"]["traffic_detail"] = {
                 "unit": "HBM bytes per main pass (calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",

@@ -68,8 +68,9 @@ def test_paper_top32_histogram_sampled_rows(paper):
 
 
 def test_mid_triangle_sampled_pairs():
-    """50,000 words, the int8 triangle of the bench: sampled pair indices, every
-    block-boundary row start and the last pairs against the oracle."""
+    """50,000 words, the int8 triangle of the bench: a random sample of 10^6 pair
+    indices, every block-boundary row start, the last pairs, and two full blocks
+    of 100 rows (all their partners) against the oracle."""
     nw = _nw()
     _report("full size: 50k int8 triangle")
     v = synth.plain_config("mid")
@@ -79,10 +80,17 @@ def test_mid_triangle_sampled_pairs():
     n, E = v.n, dv.num_pairs
     rng = np.random.default_rng(3)
     starts = [index_map.S(n, r - 1) for r in range(0, n - 1, 1024)]
-    idx = np.unique(np.concatenate([rng.integers(0, E, 100_000), starts, np.arange(E - 50, E), np.arange(0, 50)]))
+    idx = np.unique(np.concatenate([rng.integers(0, E, 1_000_000), starts, np.arange(E - 50, E), np.arange(0, 50)]))
     got = out[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int32)
-    pi, pj = _pairs_of(n, idx)
-    np.testing.assert_array_equal(got, oracle.pairs(v.symbols, v.offsets, _pm1(), -1, pi, pj))
+    # rows from the integer row starts S_r (the index map pinned in test_index_map)
+    rows = np.searchsorted(np.array([index_map.S(n, r) for r in range(n - 1)], np.int64), idx, side="right")
+    cols = rows + 1 + idx - np.array([index_map.S(n, r - 1) for r in rows.tolist()], np.int64)
+    np.testing.assert_array_equal(got, oracle.pairs(v.symbols, v.offsets, _pm1(), -1, rows, cols))
+    for r0 in (0, 24950):
+        b0, b1 = index_map.S(n, r0 - 1), index_map.S(n, r0 + 99)
+        np.testing.assert_array_equal(out[b0:b1].cpu().numpy().astype(np.int32),
+                                      oracle.triangle(v.symbols, v.offsets, _pm1(), -1, b0, b1),
+                                      err_msg=f"rows {r0}..{r0 + 99}")
 
 
 def test_batched_full_config_sampled_pairs():
