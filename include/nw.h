@@ -108,8 +108,10 @@ int nw_score_bounds(const nw_vocab *v, int32_t *lo, int32_t *hi);
  * proposes for going past device memory (Section 5).  d_out holds
  * (idx_end - idx_begin) elements of dt (int8 or int16), row-major triangle
  * order, in the caller's word order.
- * Errors: NW_EINVAL (idx_begin > idx_end or idx_end > E, bad dtype),
- * NW_ERANGE (the score bounds do not fit dt). */
+ * Errors: NW_EINVAL (NULL vocab, idx_begin > idx_end or idx_end > E, bad
+ * dtype, NULL d_out with a non-empty range, a similarity matrix that is not
+ * symmetric -- the unordered pairs need score(i, j) = score(j, i)),
+ * NW_ERANGE (the score bounds do not fit dt), NW_EDEVICE. */
 int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
                         void *d_out, void *hip_stream);
 
@@ -187,8 +189,9 @@ typedef struct {
  * entries each (they may be NULL when cap == 0, to count only).  Enqueued
  * on hip_stream; the results are valid once it has synchronised.
  * Errors: NW_EINVAL (NULL vocab, filter or d_count, d_count not 8-byte or
- * the arrays not naturally aligned, mode not one of nw_edge_mode, lo > hi, den outside 1..1000000 for the normalised mode, a
- * range outside [0, n(n-1)/2], an asymmetric similarity), NW_EDEVICE. */
+ * the arrays not naturally aligned, mode not one of nw_edge_mode, lo > hi,
+ * den outside 1..1000000 for the normalised mode, a range outside
+ * [0, n(n-1)/2], an asymmetric similarity), NW_EDEVICE. */
 int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, const nw_edge_filter *f,
                        int32_t *d_i, int32_t *d_j, int16_t *d_score, uint64_t cap, uint64_t *d_count,
                        void *hip_stream);
@@ -211,8 +214,9 @@ int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes);
  * histogram of raw edge weights of Section 5.  Every unordered pair is scored
  * once.  d_ws: nw_topk_workspace_bytes() bytes, 256-byte aligned, caller-owned.
  * Synchronous: returns once the results are complete on hip_stream.
- * Errors: NW_EINVAL (k outside 1..63, asymmetric similarity), NW_ENOMEM
- * (workspace too small). */
+ * Errors: NW_EINVAL (k outside 1..63, asymmetric similarity, words longer
+ * than 48 symbols, NULL or misaligned buffers), NW_ENOMEM (workspace too
+ * small), NW_EDEVICE. */
 int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist,
                       void *d_ws, uint64_t ws_bytes, void *hip_stream);
 
