@@ -5,6 +5,7 @@
 #include <utility>
 
 #include "k_batch.h"
+#include "k_edges.h"
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_tri_tiled.h"
@@ -21,6 +22,7 @@ static void fill(KernelTables &t, std::integer_sequence<int, Is...>)
     ((t.tri[LO + Is] = reinterpret_cast<const void *>(&k_tri_tiled<LO + Is>)), ...);
     ((t.query[LO + Is] = reinterpret_cast<const void *>(&k_query_tiled<LO + Is>)), ...);
     ((t.topk[LO + Is] = reinterpret_cast<const void *>(&k_topk_tiled<LO + Is>)), ...);
+    ((t.edges[LO + Is] = reinterpret_cast<const void *>(&k_edges_tiled<LO + Is>)), ...);
     ((t.persist1[LO + Is] = reinterpret_cast<const void *>(&k_tri_persist<LO + Is, LO + Is>)), ...);
 }
 

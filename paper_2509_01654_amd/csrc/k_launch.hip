@@ -9,6 +9,7 @@
 
 #include "k_batch.h"
 #include "k_diag.h"
+#include "k_edges.h"
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_tri_tiled.h"
@@ -115,26 +116,30 @@ static TriGrid tri_grid(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end)
     return {(uint32_t)all, 0, 0};
 }
 
+// How many runs of row pairs a launch of `tiles` tiles cuts each tile of a
+// row length into (at most maxrp row pairs per tile).  A launch with fewer
+// tiles than workgroup slots (256 CUs x 6) splits its tiles into runs of at
+// least kMinRowPairs row pairs, up to about four workgroups per slot; short
+// runs cost more than they balance.
+static uint32_t tile_chunks(uint64_t tiles, uint32_t maxrp)
+{
+    constexpr uint64_t kTargetWorkgroups = 256 * 6 * 4;
+    constexpr uint64_t kSplitBelow = 2048;
+    constexpr uint32_t kMinRowPairs = 8;
+    if (tiles >= kSplitBelow) return 1;
+    const uint32_t want = (uint32_t)((kTargetWorkgroups + tiles - 1) / tiles);
+    return std::max<uint32_t>(1, std::min(want, maxrp / kMinRowPairs));
+}
+
 hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
                                  int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E)
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
-    // A launch with fewer tiles than workgroup slots (256 CUs x 6) splits its
-    // tiles into runs of at least kMinRowPairs row pairs, up to about four
-    // workgroups per slot; short runs cost more than they balance.
-    constexpr uint64_t kTargetWorkgroups = 256 * 6 * 4;
-    constexpr uint64_t kSplitBelow = 2048;
-    constexpr uint32_t kMinRowPairs = 8;
     for (int LA = 0; LA <= V.lmax; ++LA) {
         if (h_maxrp[LA] == 0) continue;   // no block has row pairs of this length
-        uint32_t chunks = 1;
-        if (G.blocks < kSplitBelow) {
-            const uint32_t want = (uint32_t)((kTargetWorkgroups + G.blocks - 1) / G.blocks);
-            const uint32_t most = h_maxrp[LA] / kMinRowPairs;
-            chunks = std::max<uint32_t>(1, std::min(want, most));
-        }
+        uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);
         uint32_t rpc = (h_maxrp[LA] + chunks - 1) / chunks;
         DevVocab Vc = V;
         uint64_t ib = idx_begin, ie = idx_end;
@@ -145,6 +150,28 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
         void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
         hipError_t e = launch_dyn(tab.tri[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
                                   tri_lds_bytes(LA, V.alphabet, V.CB), stream, args);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
+                              const EdgeSink &E, hipStream_t stream)
+{
+    if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
+    const TriGrid G = tri_grid(V, idx_begin, idx_end);
+    const KernelTables &tab = kernel_tables();
+    for (int LA = 0; LA <= V.lmax; ++LA) {
+        if (h_maxrp[LA] == 0) continue;
+        uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);
+        uint32_t rpc = (h_maxrp[LA] + chunks - 1) / chunks;
+        DevVocab Vc = V;
+        EdgeSink Ec = E;
+        uint64_t ib = idx_begin, ie = idx_end;
+        uint32_t rb0 = G.rb0, rbn = G.rbn;
+        void *args[] = {&Vc, &Ec, &ib, &ie, &rb0, &rbn, &chunks, &rpc};
+        hipError_t e = launch_dyn(tab.edges[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
+                                  edges_lds_bytes(LA, V.alphabet, V.CB), stream, args);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -611,7 +611,7 @@ int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, 
     E.hi = f->hi;
     E.den = f->mode == NW_EDGE_NORMALISED ? f->den : 1;
     e = v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, idx_begin, idx_end, OUT_EDGES, nullptr, st, &E)
-                                       : launch_triangle_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, OUT_EDGES, nullptr, st, &E);
+                                       : launch_edges_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, E, st);
     if (e != hipSuccess) return dev_fail(e, "launching the edge kernels");
     return ok();
 }

@@ -98,6 +98,10 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
                                  int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
                                  void *d_out, hipStream_t stream);
+// Threshold edges of pair indices [idx_begin, idx_end) into E, scored and
+// tested in registers (words of at most kMaxLen symbols).
+hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
+                              const EdgeSink &E, hipStream_t stream);
 // Anti-diagonal (16 lanes per pair) kernel, words up to 256 symbols.
 hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
                                 void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);

@@ -17,6 +17,7 @@ struct KernelTables {
     const void *tri[kMaxLen + 1];
     const void *query[kMaxLen + 1];
     const void *topk[kMaxLen + 1];
+    const void *edges[kMaxLen + 1];      // threshold edge emitter
     const void *persist1[kMaxLen + 1];   // persistent batched kernel, one per row length
     const void *persist8[kNumClass8];    // persistent batched kernel, one per class of 8 lengths
 };
