@@ -2,41 +2,56 @@
 //
 // The stencil the paper points to as the way to parallelise inside one score
 // matrix (Section 6: each cell depends on its up, left and up-left
-// neighbours, Section 4.2).  A group of 16 lanes shares one column word; lane
-// t owns the R consecutive rows t*R+1 .. t*R+R of the DP (the same binary16
-// recurrence G of nw_dp.h, two row words in the two halves).  At step s lane
-// t processes column s - t, so the 16 lanes work on one anti-diagonal band:
-// the cell above a lane's first row is the last row of lane t-1 one step
-// earlier, and the diagonal neighbour is that value one step before, passed
-// down the group with a DPP row shift (lane 0 of each 16-lane row receives
-// 0, the G[0][j] boundary).  Columns before the start (s - t < 0) and past the
-// end of the word read the sentinel symbol, whose profile row leaves a DP
-// column unchanged (nw_dp.h), so every lane runs every step with no branch.
+// neighbours, Section 4.2).  A group of 16 lanes (one DPP row) shares one
+// column word; lane t owns the R consecutive rows t*R+1 .. t*R+R of the DP
+// (the binary16 recurrence G of nw_dp.h, two row words in the two halves).
+// At step s lane t processes column s - t, so the 16 lanes work on one
+// anti-diagonal band: the cell above a lane's first row is the last row of
+// lane t-1 one step earlier, and the diagonal neighbour is that value one step
+// before, passed down the group with a DPP row shift (lane 0 of each row
+// receives 0, the G[0][j] boundary).  Columns before the start (s - t < 0) and
+// past the end of the word read the sentinel symbol, whose profile row leaves
+// a DP column unchanged (nw_dp.h), so every lane runs every step with no
+// branch.
 //
-// Rows per lane R is a template parameter (16*R rows cover words up to 16*R
-// symbols); a row pair of length LA <= 16*R runs in class R, and the score is
-// read from row LA of the final column.  The similarity profile of the row
-// pair spans 16*R positions (positions >= LA are never read into rows <= LA).
+// One launch per class R (rows per lane, a multiple of 4): the class takes
+// the row lengths LA with 16(R-4) < LA <= 16R, and a workgroup takes a tile
+// (block pair r <= b) and a run of its row pairs of those lengths (they are
+// contiguous in the row-pair table).  1024 threads = 64 groups share one
+// similarity profile of the current row pair in LDS, laid out so that the 16
+// lanes of a group read 16 consecutive 16-byte units whatever symbols they
+// look up (the 64 LDS banks once each); symbols and profile entries are read
+// one step ahead of the DP.  The score of a pair is row LA of the final
+// column.
 #pragma once
 
 #include "nw_tile_common.h"
 
 namespace nw {
 
-constexpr int kDiagLanes = 16;        // lanes per pair
-constexpr int kDiagMaxLen = 255;      // longest word of the anti-diagonal path
-constexpr int kDiagBuf = 16 + kDiagMaxLen + 16 + 16;   // sentinel | word | sentinel (+ pad)
+constexpr int kDiagLanes = 16;                          // lanes per pair
+constexpr int kDiagThreads = 1024;                      // threads per workgroup
+constexpr int kDiagGroups = kDiagThreads / kDiagLanes;  // column words in flight per workgroup
+constexpr int kDiagMaxLen = 255;                        // longest word of the anti-diagonal path
+// Group word buffer: 16 sentinels | the padded word (at most 256 bytes) | 16 sentinels.
+constexpr int kDiagBuf = 16 + 256 + 16;
+// Largest workgroup LDS of the device.
+constexpr uint32_t kDiagMaxLds = 160u * 1024u;
 
-__host__ __device__ constexpr uint32_t diag_stride_dw(int R) { return (uint32_t)((((kDiagLanes * R) / 4) | 1) * 4); }
+// Dwords per profile row (one symbol): 16R, a multiple of 64 (R % 4 == 0).
+__host__ __device__ constexpr uint32_t diag_stride_dw(int R) { return (uint32_t)(kDiagLanes * R); }
 __host__ __device__ constexpr uint32_t diag_prof_bytes(int R, int alphabet)
 {
     return (uint32_t)(alphabet + 1) * diag_stride_dw(R) * 4u;
 }
-// LDS: one profile, three int16 staging row pairs, 16 group word buffers.
+// LDS: one profile, two int16 staging row pairs, the group word buffers.
 __host__ __device__ constexpr uint32_t diag_lds_bytes(int R, int alphabet, int CB)
 {
-    return diag_prof_bytes(R, alphabet) + 3u * 2u * (uint32_t)CB * 2u + 16u * kDiagBuf;
+    return diag_prof_bytes(R, alphabet) + 2u * 2u * (uint32_t)CB * 2u + (uint32_t)kDiagGroups * kDiagBuf;
 }
+// Rows per lane of row length LA (1 <= LA <= 255): the smallest multiple of 4
+// whose 16 lanes cover LA rows.
+__host__ __device__ constexpr int diag_class(int LA) { return ((LA + 63) / 64) * 4; }
 
 __device__ __forceinline__ uint32_t dpp_row_shr1(uint32_t v)
 {
@@ -44,19 +59,37 @@ __device__ __forceinline__ uint32_t dpp_row_shr1(uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
 }
 
+// Profile entry of lane t, its row q*4 + e (0 <= e < 4) within the lane, for
+// symbol c: dword c*16R + q*64 + t*4 + e.
 template <int R>
-__global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
-                                                       int out_kind, EdgeSink E, int LA, uint32_t rb0, uint32_t rbn)
+__device__ __forceinline__ void diag_load(u32x4 (&w)[R / 4], const uint32_t *prof_t, uint32_t sym)
 {
+    const u32x4 *row = reinterpret_cast<const u32x4 *>(prof_t + sym * diag_stride_dw(R));
+#pragma unroll
+    for (int q = 0; q < R / 4; ++q) w[q] = row[q * kDiagLanes];
+}
+
+template <int R>
+__global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t idx_begin, uint64_t idx_end,
+                                                           void *out, int out_kind, EdgeSink E, int la_lo, int la_hi,
+                                                           uint32_t rb0, uint32_t rbn, uint32_t chunks, uint32_t rpc)
+{
+    static_assert(R % 4 == 0 && R >= 4 && R <= 16, "rows per lane");
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr uint32_t S = diag_stride_dw(R);
     constexpr int ROWS = kDiagLanes * R;
+    constexpr int Q = R / 4;
 
     uint32_t r, b;
-    if (!tile_block_pair(blockIdx.x, rb0, rbn, V.nb, r, b)) return;
-    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
-    const uint32_t pbeg = rpo[0], pend = rpo[1];
-    if (pbeg >= pend) return;
+    if (!tile_block_pair(blockIdx.x / chunks, rb0, rbn, V.nb, r, b)) return;
+    // the row pairs of block r with lengths la_lo..la_hi, cut into runs of rpc
+    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1);
+    const uint32_t cbeg = rpo[la_lo], cend = rpo[la_hi + 1];
+    const uint64_t pbeg64 = (uint64_t)cbeg + (uint64_t)(blockIdx.x % chunks) * rpc;
+    if (pbeg64 >= cend) return;
+    const uint32_t pbeg = (uint32_t)pbeg64;
+    const uint32_t pend = cend - pbeg <= rpc ? cend : pbeg + rpc;
+
     const int64_t n = V.n, CB = V.CB;
     const int64_t I0 = (int64_t)r * CB, I1 = min(I0 + CB, n);
     const int64_t J0 = (int64_t)b * CB, J1 = min(J0 + CB, n);
@@ -70,24 +103,33 @@ __global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_
     }
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int t = tid & (kDiagLanes - 1);          // position in the group
-    const int g = tid / kDiagLanes;                // group 0..15 of the workgroup
+    const int t = tid & (kDiagLanes - 1);   // position in the group
+    const int g = tid / kDiagLanes;         // group of the workgroup
     const int A = V.alphabet;
     uint32_t *prof = reinterpret_cast<uint32_t *>(lds);
-    int16_t *stg = reinterpret_cast<int16_t *>(lds + diag_prof_bytes(R, A));   // [3][2][CB]
-    uint8_t *gbuf = lds + diag_prof_bytes(R, A) + 3 * 2 * CB * 2 + g * kDiagBuf;
-    const int tstar = (LA - 1) / R;                // lane holding row LA
-    const int istar = (LA - 1) % R;
+    int16_t *stg = reinterpret_cast<int16_t *>(lds + diag_prof_bytes(R, A));   // [2][2][CB]
+    uint8_t *gbuf_all = lds + diag_prof_bytes(R, A) + 2 * 2 * CB * 2;
+    uint8_t *gbuf = gbuf_all + g * kDiagBuf;
+    const uint32_t *prof_t = prof + t * 4;
+    const int wq = V.WB / 16;               // 16-byte units of a padded word
 
-    for (uint32_t k = pbeg; k < pend + 2; ++k) {
-        __syncthreads();   // the previous pair's DP has finished reading the profile
+    // every group buffer starts as sentinels; a column only rewrites its word
+    {
+        const uint32_t sent4 = (uint32_t)A * 0x01010101u;
+        uint32_t *p = reinterpret_cast<uint32_t *>(gbuf_all);
+        for (int e = tid; e < kDiagGroups * kDiagBuf / 4; e += kDiagThreads) p[e] = sent4;
+    }
+
+    for (uint32_t k = pbeg; k <= pend; ++k) {
+        __syncthreads();   // the previous DP has finished with the profile and its staging rows
         if (k < pend) {
             const int32_t a0 = V.rpairs[2 * k], a1 = V.rpairs[2 * k + 1];
+            const int LA = V.blen[a0];
             const uint8_t *su = V.bsym + (int64_t)a0 * V.WB;
             const uint8_t *su2 = V.bsym + (int64_t)(a1 >= 0 ? a1 : a0) * V.WB;
-            for (int e = tid; e < (A + 1) * ROWS; e += kThreads) {
+            for (int e = tid; e < (A + 1) * ROWS; e += kDiagThreads) {
                 const int c = e / ROWS, i = e - c * ROWS;
+                const int lt = i / R, ri = i - lt * R;
                 uint32_t val;
                 if (c == A)
                     val = kSentinelPair;
@@ -95,44 +137,48 @@ __global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_
                     val = (uint32_t)V.wtab[(int)su[i] * A + c] | ((uint32_t)V.wtab[(int)su2[i] * A + c] << 16);
                 else
                     val = 0;
-                prof[c * S + i] = val;
+                prof[c * S + (ri >> 2) * (4 * kDiagLanes) + lt * 4 + (ri & 3)] = val;
             }
         }
-        if (k >= pbeg + 2) {
-            const uint32_t kk = k - 2;
-            const int16_t *srow = stg + (size_t)(kk % 3) * 2 * CB;
+        if (k > pbeg) {
+            const uint32_t kk = k - 1;
+            const int LA = V.blen[V.rpairs[2 * kk]];
+            const int16_t *srow = stg + (size_t)(kk & 1) * 2 * CB;
             for (int h = 0; h < 2; ++h) {
                 const int32_t slot = V.rpairs[2 * kk + h];
                 if (slot < 0) continue;
                 const int64_t u = I0 + V.bcol[slot];
                 const int64_t jstart = (r == b) ? u + 1 : J0;
-                store_row(V, u, LA, jstart, J1, srow + h * CB + (jstart - J0), idx_begin, idx_end, out, out_kind, E);
+                store_row<kDiagThreads>(V, u, LA, jstart, J1, srow + h * CB + (jstart - J0), idx_begin, idx_end,
+                                        out, out_kind, E);
             }
         }
         __syncthreads();
-        if (k >= pend) continue;
+        if (k == pend) break;
+
         const int32_t a1 = V.rpairs[2 * k + 1];
-        int16_t *sdst = stg + (size_t)(k % 3) * 2 * CB;
-        for (int64_t c0 = 0; c0 < CB; c0 += kThreads / kDiagLanes) {
+        const int LA = V.blen[V.rpairs[2 * k]];
+        const int tstar = (LA - 1) / R;     // lane holding row LA
+        const int istar = (LA - 1) % R;
+        int16_t *sdst = stg + (size_t)(k & 1) * 2 * CB;
+        // the first column word of this group, prefetched
+        u32x4 wnext = u32x4{0, 0, 0, 0};
+        if (t < wq) wnext = *reinterpret_cast<const u32x4 *>(V.bsym + (J0 + g) * V.WB + 16 * t);
+        for (int64_t c0 = 0; c0 < CB; c0 += kDiagGroups) {
             const int64_t slot = J0 + c0 + g;
+            if (t < wq) *reinterpret_cast<u32x4 *>(gbuf + 16 + 16 * t) = wnext;
+            {
+                // next column word of the group (clamped to the block: always a valid slot)
+                const int64_t ns = J0 + min(c0 + kDiagGroups, CB - kDiagGroups) + g;
+                if (t < wq) wnext = *reinterpret_cast<const u32x4 *>(V.bsym + ns * V.WB + 16 * t);
+            }
             const int lb = V.blen[slot];
             const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);   // slots ascend in length
-            // the group's word between sentinels: gbuf[16 + j] = B[j]
-            for (int q = t; q < kDiagBuf; q += kDiagLanes) {
-                const int j = q - 16;
-                gbuf[q] = (j >= 0 && j < lb) ? V.bsym[slot * V.WB + j] : (uint8_t)A;
-            }
             h2 col[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) col[i] = h2{0, 0};
             uint32_t last = 0, diag_in = 0;
-            const int steps = lbmax_w + kDiagLanes - 1;
-            for (int s = 0; s < steps; ++s) {
-                const uint32_t sym = gbuf[16 + s - t];
-                const u32x4 *row = reinterpret_cast<const u32x4 *>(prof + sym * S + t * R);
-                u32x4 w[(R + 3) / 4];
-#pragma unroll
-                for (int q = 0; q < (R + 3) / 4; ++q) w[q] = row[q];
+            auto step = [&](const u32x4(&w)[Q]) __attribute__((always_inline)) {
                 const uint32_t up_in = dpp_row_shr1(last);
                 h2 d = as_h2(diag_in);
                 h2 up = as_h2(up_in);
@@ -145,6 +191,19 @@ __global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_
                 }
                 last = __builtin_bit_cast(uint32_t, col[R - 1]);
                 diag_in = up_in;
+            };
+            // gbuf[16 + j] = B[j]; lane t reads position s - t at step s (one step ahead:
+            // at most 16 + lbmax + 15 < kDiagBuf)
+            const uint8_t *gs = gbuf + 16 - t;
+            const int steps = lbmax_w + kDiagLanes - 1;
+            u32x4 wa[Q], wb[Q];
+            diag_load<R>(wa, prof_t, gs[0]);
+            for (int s = 0; s < steps; s += 2) {
+                diag_load<R>(wb, prof_t, gs[s + 1]);
+                step(wa);
+                if (s + 1 >= steps) break;
+                diag_load<R>(wa, prof_t, gs[s + 2]);
+                step(wb);
             }
             // row LA of the final column lives in lane tstar, register istar
             h2 res = col[0];
@@ -158,7 +217,6 @@ __global__ __launch_bounds__(kThreads) void k_tri_diag(DevVocab V, uint64_t idx_
             }
         }
     }
-    (void)lane;
 }
 
 }  // namespace nw

@@ -17,9 +17,11 @@
 
 namespace nw {
 
-// CAP: scratch row capacity (longest word + 1); NT: threads per block.
-template <typename OutT, int CAP, int NT>
-__global__ __launch_bounds__(NT) void k_tri_naive(DevVocab V, uint64_t idx_begin, uint64_t idx_end, OutT *out)
+// CAP: scratch row capacity (longest word + 1); NT: threads per block.  The
+// score goes to out (OUT_I8 / OUT_I16) or, if it passes the slice, to E.
+template <int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_tri_naive(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
+                                                  int out_kind, EdgeSink E)
 {
     __shared__ int16_t rows[NT][CAP];
     int16_t *row = rows[threadIdx.x];   // this thread's scratch: one row of the score matrix
@@ -55,7 +57,13 @@ __global__ __launch_bounds__(NT) void k_tri_naive(DevVocab V, uint64_t idx_begin
                 row[j] = (int16_t)v;
             }
         }
-        out[idx - idx_begin] = (OutT)row[lb];
+        const int score = row[lb];
+        if (out_kind == OUT_I8)
+            static_cast<int8_t *>(out)[idx - idx_begin] = (int8_t)score;
+        else if (out_kind == OUT_I16)
+            static_cast<int16_t *>(out)[idx - idx_begin] = (int16_t)score;
+        else if (edge_passes(E, score, la, lb))
+            edge_direct(E, (int32_t)r, (int32_t)c, score);
     }
 }
 
@@ -178,7 +186,7 @@ hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64
 }
 
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
-                                 hipStream_t stream)
+                                 hipStream_t stream, const EdgeSink *E)
 {
     if (idx_begin >= idx_end) return hipSuccess;
     const uint64_t count = idx_end - idx_begin;
@@ -186,50 +194,67 @@ hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t
     const uint64_t nt = lng ? 64 : 256;
     const uint64_t blocks = (count + nt - 1) / nt;
     const uint32_t grid = (uint32_t)(blocks < (1u << 20) ? blocks : (1u << 20));
-    if (!lng && out_kind == OUT_I8)
-        hipLaunchKernelGGL((k_tri_naive<int8_t, kMaxLen + 1, 256>), dim3(grid), dim3(256), 0, stream, V, idx_begin,
-                           idx_end, (int8_t *)d_out);
-    else if (!lng)
-        hipLaunchKernelGGL((k_tri_naive<int16_t, kMaxLen + 1, 256>), dim3(grid), dim3(256), 0, stream, V, idx_begin,
-                           idx_end, (int16_t *)d_out);
-    else if (out_kind == OUT_I8)
-        hipLaunchKernelGGL((k_tri_naive<int8_t, kLongMaxLen + 1, 64>), dim3(grid), dim3(64), 0, stream, V, idx_begin,
-                           idx_end, (int8_t *)d_out);
+    const EdgeSink es = E ? *E : EdgeSink{};
+    if (!lng)
+        hipLaunchKernelGGL((k_tri_naive<kMaxLen + 1, 256>), dim3(grid), dim3(256), 0, stream, V, idx_begin, idx_end,
+                           d_out, out_kind, es);
     else
-        hipLaunchKernelGGL((k_tri_naive<int16_t, kLongMaxLen + 1, 64>), dim3(grid), dim3(64), 0, stream, V, idx_begin,
-                           idx_end, (int16_t *)d_out);
+        hipLaunchKernelGGL((k_tri_naive<kLongMaxLen + 1, 64>), dim3(grid), dim3(64), 0, stream, V, idx_begin, idx_end,
+                           d_out, out_kind, es);
     return hipGetLastError();
 }
 
-hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
-                                hipStream_t stream, const EdgeSink *E)
+// Row lengths of anti-diagonal class R (rows per lane): (16(R-4), 16R].
+static int diag_la_lo(int R) { return kDiagLanes * (R - 4) + 1; }
+static int diag_la_hi(int R) { return kDiagLanes * R; }
+
+bool diag_fits(const DevVocab &V)
+{
+    for (int R = 4; R <= 16; R += 4)
+        if (diag_la_lo(R) <= V.lmax && diag_lds_bytes(R, V.alphabet, V.CB) > kDiagMaxLds) return false;
+    return true;
+}
+
+hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
+                                int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E)
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
+    // a class whose profile does not fit in LDS (large alphabets with long
+    // words): the whole range goes through the one-thread-per-pair kernel
+    if (!diag_fits(V)) return launch_triangle_naive(V, idx_begin, idx_end, out_kind, d_out, stream, E);
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
-    for (int LA = 0; LA <= V.lmax; ++LA) {
-        DevVocab Vc = V;
-        uint64_t ib = idx_begin, ie = idx_end;
-        void *po = d_out;
-        int ok = out_kind;
-        EdgeSink es = E ? *E : EdgeSink{};
-        uint32_t rb0 = G.rb0, rbn = G.rbn;
-        hipError_t e;
-        if (LA == 0) {
-            uint32_t one = 1, all = 0xFFFFFFFFu;
-            void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &one, &all};
-            e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
-        } else {
-            // rows per lane: the smallest class whose 16 lanes cover LA rows
-            const int R = LA <= 64 ? 4 : LA <= 128 ? 8 : LA <= 192 ? 12 : 16;
-            const void *fn = R == 4 ? reinterpret_cast<const void *>(&k_tri_diag<4>)
-                           : R == 8 ? reinterpret_cast<const void *>(&k_tri_diag<8>)
-                           : R == 12 ? reinterpret_cast<const void *>(&k_tri_diag<12>)
-                                     : reinterpret_cast<const void *>(&k_tri_diag<16>);
-            int la = LA;
-            void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &la, &rb0, &rbn};
-            e = launch_dyn(fn, dim3(G.blocks), diag_lds_bytes(R, V.alphabet, V.CB), stream, args);
-        }
+    DevVocab Vc = V;
+    uint64_t ib = idx_begin, ie = idx_end;
+    void *po = d_out;
+    int ok = out_kind;
+    EdgeSink es = E ? *E : EdgeSink{};
+    uint32_t rb0 = G.rb0, rbn = G.rbn;
+    if (h_maxrp[0] != 0) {   // empty row words: score gap * lb, the register-row kernel of length 0
+        uint32_t one = 1, all = 0xFFFFFFFFu;
+        void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &one, &all};
+        hipError_t e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
+        if (e != hipSuccess) return e;
+    }
+    for (int R = 4; R <= 16; R += 4) {
+        int la_lo = diag_la_lo(R), la_hi = std::min(diag_la_hi(R), (int)V.lmax);
+        if (la_lo > la_hi) break;
+        uint64_t maxrp = 0;   // bound on the row pairs of one block in this class
+        for (int LA = la_lo; LA <= la_hi; ++LA) maxrp += h_maxrp[LA];
+        if (maxrp == 0) continue;
+        // runs of row pairs so that a launch has about kDiagWorkgroups workgroups
+        constexpr uint64_t kDiagWorkgroups = 2048;
+        uint32_t chunks = (uint32_t)std::min<uint64_t>(maxrp, std::max<uint64_t>(1, (kDiagWorkgroups + G.blocks - 1) / G.blocks));
+        uint32_t rpc = (uint32_t)((maxrp + chunks - 1) / chunks);
+        const void *fn = R == 4 ? reinterpret_cast<const void *>(&k_tri_diag<4>)
+                       : R == 8 ? reinterpret_cast<const void *>(&k_tri_diag<8>)
+                       : R == 12 ? reinterpret_cast<const void *>(&k_tri_diag<12>)
+                                 : reinterpret_cast<const void *>(&k_tri_diag<16>);
+        void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &la_lo, &la_hi, &rb0, &rbn, &chunks, &rpc};
+        const size_t lds = diag_lds_bytes(R, V.alphabet, V.CB);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        e = hipLaunchKernel(fn, dim3((uint32_t)((uint64_t)G.blocks * chunks)), dim3(kDiagThreads), args, lds, stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

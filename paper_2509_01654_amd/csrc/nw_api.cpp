@@ -280,7 +280,7 @@ hipError_t nw::host::launch_triangle(const nw_vocab *v, uint64_t idx_begin, uint
 {
     // words longer than the register-row limit take the anti-diagonal kernel
     const int kind = dt == NW_I8 ? OUT_I8 : OUT_I16;
-    return v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, idx_begin, idx_end, kind, d_out, stream)
+    return v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, v->h_maxrp.data(), idx_begin, idx_end, kind, d_out, stream)
                                           : launch_triangle_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, kind, d_out, stream);
 }
 
@@ -561,7 +561,7 @@ int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx
 {
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
     if (rc) return rc;
-    hipError_t e = launch_triangle_diag(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
+    hipError_t e = launch_triangle_diag(v->dev, v->h_maxrp.data(), idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
                                         (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the anti-diagonal triangle kernel");
     return ok();
@@ -610,7 +610,7 @@ int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, 
     E.lo = f->lo;
     E.hi = f->hi;
     E.den = f->mode == NW_EDGE_NORMALISED ? f->den : 1;
-    e = v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, idx_begin, idx_end, OUT_EDGES, nullptr, st, &E)
+    e = v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, v->h_maxrp.data(), idx_begin, idx_end, OUT_EDGES, nullptr, st, &E)
                                        : launch_edges_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, E, st);
     if (e != hipSuccess) return dev_fail(e, "launching the edge kernels");
     return ok();

@@ -97,14 +97,17 @@ struct EdgeSink {
 hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
                                  int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
-                                 void *d_out, hipStream_t stream);
+                                 void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
 // Threshold edges of pair indices [idx_begin, idx_end) into E, scored and
 // tested in registers (words of at most kMaxLen symbols).
 hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
                               const EdgeSink &E, hipStream_t stream);
-// Anti-diagonal (16 lanes per pair) kernel, words up to 256 symbols.
-hipError_t launch_triangle_diag(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind,
-                                void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
+// Anti-diagonal (16 lanes per pair) kernel, words up to 255 symbols; one
+// launch per class of row lengths.  A dictionary whose longest words need a
+// profile larger than LDS (diag_fits false) is scored by the naive kernel.
+bool diag_fits(const DevVocab &V);
+hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
+                                int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
 
 // Per-row top-k lists of the rows R (pairs grouped by length, h_off = host
 // copy of R.off) against the column set C, split over nsplit column ranges:

@@ -164,7 +164,9 @@ __device__ __forceinline__ bool edge_passes(const EdgeSink &E, int s, int la, in
 // idx_begin] (int8 / int16), or as edges into E (OUT_EDGES).  Edges take one
 // atomic per wavefront and row that has any: the wavefront counts its passing
 // pairs with ballots, reserves that many slots, then writes them in the same
-// order.  Every thread of the workgroup calls this with the same arguments.
+// order.  Every thread of the workgroup (NT threads) calls this with the same
+// arguments.
+template <int NT = kThreads>
 __device__ __forceinline__ void store_row(const DevVocab &V, int64_t u, int la, int64_t jstart, int64_t J1,
                                           const int16_t *srow, uint64_t idx_begin, uint64_t idx_end, void *out,
                                           int out_kind, const EdgeSink &E)
@@ -173,7 +175,7 @@ __device__ __forceinline__ void store_row(const DevVocab &V, int64_t u, int la, 
     const int64_t len = J1 - jstart;
     const int tid = threadIdx.x;
     if (out_kind != OUT_EDGES) {
-        for (int64_t t = tid; t < len; t += kThreads) {
+        for (int64_t t = tid; t < len; t += NT) {
             const uint64_t idx = base + (uint64_t)t;
             if (idx >= idx_begin && idx < idx_end) {
                 const int16_t s = srow[t];
@@ -193,7 +195,7 @@ __device__ __forceinline__ void store_row(const DevVocab &V, int64_t u, int la, 
     };
     // the trip count is uniform over the wavefront, so every ballot sees all 64 lanes
     uint32_t cnt = 0;
-    for (int64_t t0 = (int64_t)wave * 64; t0 < len; t0 += kThreads) cnt += (uint32_t)__popcll(__ballot(passes(t0 + lane)));
+    for (int64_t t0 = (int64_t)wave * 64; t0 < len; t0 += NT) cnt += (uint32_t)__popcll(__ballot(passes(t0 + lane)));
     if (cnt == 0) return;
     uint32_t plo = 0, phi = 0;
     if (lane == 0) {
@@ -203,7 +205,7 @@ __device__ __forceinline__ void store_row(const DevVocab &V, int64_t u, int la, 
     }
     uint64_t pos = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)plo) |
                    ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)phi) << 32);
-    for (int64_t t0 = (int64_t)wave * 64; t0 < len; t0 += kThreads) {
+    for (int64_t t0 = (int64_t)wave * 64; t0 < len; t0 += NT) {
         const int64_t t = t0 + lane;
         const bool p = passes(t);
         const uint64_t m = __ballot(p);
