@@ -12,7 +12,10 @@
 // receives 0, the G[0][j] boundary).  Columns before the start (s - t < 0) and
 // past the end of the word read the sentinel symbol, whose profile row leaves
 // a DP column unchanged (nw_dp.h), so every lane runs every step with no
-// branch.
+// branch.  The column symbols flow down the group the same way: lane t needs
+// at step s the symbol lane t-1 had at step s-1, so one DPP row shift per step
+// hands them on, and lane 0 takes the next symbol of the word from an aligned
+// dword of LDS read once per four steps.
 //
 // One launch per class R (rows per lane, a multiple of 4): the class takes
 // the row lengths LA with 16(R-4) < LA <= 16R, and a workgroup takes a tile
@@ -33,8 +36,8 @@ constexpr int kDiagLanes = 16;                          // lanes per pair
 constexpr int kDiagThreads = 1024;                      // threads per workgroup
 constexpr int kDiagGroups = kDiagThreads / kDiagLanes;  // column words in flight per workgroup
 constexpr int kDiagMaxLen = 255;                        // longest word of the anti-diagonal path
-// Group word buffer: 16 sentinels | the padded word (at most 256 bytes) | 16 sentinels.
-constexpr int kDiagBuf = 16 + 256 + 16;
+// Group word buffer: the padded word (at most 256 bytes) | 32 sentinels.
+constexpr int kDiagBuf = 256 + 32;
 // Largest workgroup LDS of the device.
 constexpr uint32_t kDiagMaxLds = 160u * 1024u;
 
@@ -58,6 +61,11 @@ __device__ __forceinline__ uint32_t dpp_row_shr1(uint32_t v)
     // row_shr:1 within rows of 16 lanes; lane 0 of a row reads 0 (bound_ctrl)
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
 }
+__device__ __forceinline__ uint32_t dpp_row_shr1_or(uint32_t first, uint32_t v)
+{
+    // row_shr:1 within rows of 16 lanes; lane 0 of a row keeps `first`
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x111, 0xF, 0xF, false);
+}
 
 // Profile entry of lane t, its row q*4 + e (0 <= e < 4) within the lane, for
 // symbol c: dword c*16R + q*64 + t*4 + e.
@@ -67,6 +75,9 @@ __device__ __forceinline__ void diag_load(u32x4 (&w)[R / 4], const uint32_t *pro
     const u32x4 *row = reinterpret_cast<const u32x4 *>(prof_t + sym * diag_stride_dw(R));
 #pragma unroll
     for (int q = 0; q < R / 4; ++q) w[q] = row[q * kDiagLanes];
+    // issue the reads here, one step before their use: keep the scheduler
+    // from sinking them next to the DP that consumes them
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int R>
@@ -111,6 +122,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
     uint8_t *gbuf_all = lds + diag_prof_bytes(R, A) + 2 * 2 * CB * 2;
     uint8_t *gbuf = gbuf_all + g * kDiagBuf;
     const uint32_t *prof_t = prof + t * 4;
+    const uint32_t *gword = reinterpret_cast<const uint32_t *>(gbuf);
     const int wq = V.WB / 16;               // 16-byte units of a padded word
 
     // every group buffer starts as sentinels; a column only rewrites its word
@@ -166,7 +178,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
         if (t < wq) wnext = *reinterpret_cast<const u32x4 *>(V.bsym + (J0 + g) * V.WB + 16 * t);
         for (int64_t c0 = 0; c0 < CB; c0 += kDiagGroups) {
             const int64_t slot = J0 + c0 + g;
-            if (t < wq) *reinterpret_cast<u32x4 *>(gbuf + 16 + 16 * t) = wnext;
+            if (t < wq) *reinterpret_cast<u32x4 *>(gbuf + 16 * t) = wnext;
             {
                 // next column word of the group (clamped to the block: always a valid slot)
                 const int64_t ns = J0 + min(c0 + kDiagGroups, CB - kDiagGroups) + g;
@@ -178,32 +190,49 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
 #pragma unroll
             for (int i = 0; i < R; ++i) col[i] = h2{0, 0};
             uint32_t last = 0, diag_in = 0;
+            // one step: row i takes its diagonal sum from the old value of row
+            // i-1 before the max3 chain overwrites it, so the column updates in place
             auto step = [&](const u32x4(&w)[Q]) __attribute__((always_inline)) {
                 const uint32_t up_in = dpp_row_shr1(last);
-                h2 d = as_h2(diag_in);
+                h2 a = as_h2(diag_in) + as_h2(w[0][0]);
                 h2 up = as_h2(up_in);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const h2 v = max3(d + as_h2(w[i >> 2][i & 3]), col[i], up);
-                    d = col[i];
-                    col[i] = v;
-                    up = v;
+                    h2 an = h2{0, 0};
+                    if (i + 1 < R) an = col[i] + as_h2(w[(i + 1) >> 2][(i + 1) & 3]);
+                    col[i] = max3(a, col[i], up);
+                    up = col[i];
+                    a = an;
                 }
                 last = __builtin_bit_cast(uint32_t, col[R - 1]);
                 diag_in = up_in;
             };
-            // gbuf[16 + j] = B[j]; lane t reads position s - t at step s (one step ahead:
-            // at most 16 + lbmax + 15 < kDiagBuf)
-            const uint8_t *gs = gbuf + 16 - t;
+            // symbol of lane t at step s: B[s - t], the sentinel before the word
+            // (and past it, from the padding); gword[m] holds B[4m .. 4m+3],
+            // read up to byte 4*(steps/4 + 1) + 3 < 256 + 32
             const int steps = lbmax_w + kDiagLanes - 1;
+            uint32_t dw = gword[0];
+            uint32_t sym = t == 0 ? (dw & 0xFFu) : (uint32_t)A;
             u32x4 wa[Q], wb[Q];
-            diag_load<R>(wa, prof_t, gs[0]);
-            for (int s = 0; s < steps; s += 2) {
-                diag_load<R>(wb, prof_t, gs[s + 1]);
+            diag_load<R>(wa, prof_t, sym);
+            for (int s = 0; s < steps; s += 4) {
+                const uint32_t dn = gword[(s >> 2) + 1];
+                sym = dpp_row_shr1_or((dw >> 8) & 0xFFu, sym);
+                diag_load<R>(wb, prof_t, sym);
                 step(wa);
                 if (s + 1 >= steps) break;
-                diag_load<R>(wa, prof_t, gs[s + 2]);
+                sym = dpp_row_shr1_or((dw >> 16) & 0xFFu, sym);
+                diag_load<R>(wa, prof_t, sym);
                 step(wb);
+                if (s + 2 >= steps) break;
+                sym = dpp_row_shr1_or(dw >> 24, sym);
+                diag_load<R>(wb, prof_t, sym);
+                step(wa);
+                if (s + 3 >= steps) break;
+                sym = dpp_row_shr1_or(dn & 0xFFu, sym);
+                diag_load<R>(wa, prof_t, sym);
+                step(wb);
+                dw = dn;
             }
             // row LA of the final column lives in lane tstar, register istar
             h2 res = col[0];
