@@ -173,19 +173,24 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
         const int tstar = (LA - 1) / R;     // lane holding row LA
         const int istar = (LA - 1) % R;
         int16_t *sdst = stg + (size_t)(k & 1) * 2 * CB;
-        // the first column word of this group, prefetched
-        u32x4 wnext = u32x4{0, 0, 0, 0};
-        if (t < wq) wnext = *reinterpret_cast<const u32x4 *>(V.bsym + (J0 + g) * V.WB + 16 * t);
-        for (int64_t c0 = 0; c0 < CB; c0 += kDiagGroups) {
-            const int64_t slot = J0 + c0 + g;
+        // Column words: chunk c holds the 64 slots c*64 .. c*64+63; the four
+        // groups of a wavefront take 4 consecutive slots (similar lengths), and
+        // the wavefront's quad rotates with c, so that every wavefront meets
+        // the same mix of lengths before the next barrier.
+        auto slot_of = [&](int64_t c) { return J0 + c * kDiagGroups + (((g >> 2) + c) & 15) * 4 + (g & 3); };
+        const int64_t nchunks = CB / kDiagGroups;
+        u32x4 wnext = u32x4{0, 0, 0, 0};   // the first column word of this group, prefetched
+        if (t < wq) wnext = *reinterpret_cast<const u32x4 *>(V.bsym + slot_of(0) * V.WB + 16 * t);
+        for (int64_t c = 0; c < nchunks; ++c) {
+            const int64_t slot = slot_of(c);
             if (t < wq) *reinterpret_cast<u32x4 *>(gbuf + 16 * t) = wnext;
             {
                 // next column word of the group (clamped to the block: always a valid slot)
-                const int64_t ns = J0 + min(c0 + kDiagGroups, CB - kDiagGroups) + g;
+                const int64_t ns = slot_of(min(c + 1, nchunks - 1));
                 if (t < wq) wnext = *reinterpret_cast<const u32x4 *>(V.bsym + ns * V.WB + 16 * t);
             }
             const int lb = V.blen[slot];
-            const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);   // slots ascend in length
+            const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);   // slots of a quad ascend in length
             h2 col[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) col[i] = h2{0, 0};
@@ -209,20 +214,22 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
             };
             // symbol of lane t at step s: B[s - t], the sentinel before the word
             // (and past it, from the padding); gword[m] holds B[4m .. 4m+3],
-            // read up to byte 4*(steps/4 + 1) + 3 < 256 + 32
+            // read up to byte 4*(steps/4 + 1) + 3 < 256 + 32.  The next dword
+            // is read after the second step's profile reads, so that fewer LDS
+            // reads than the wait counter tracks separate it from its use.
             const int steps = lbmax_w + kDiagLanes - 1;
             uint32_t dw = gword[0];
             uint32_t sym = t == 0 ? (dw & 0xFFu) : (uint32_t)A;
             u32x4 wa[Q], wb[Q];
             diag_load<R>(wa, prof_t, sym);
             for (int s = 0; s < steps; s += 4) {
-                const uint32_t dn = gword[(s >> 2) + 1];
                 sym = dpp_row_shr1_or((dw >> 8) & 0xFFu, sym);
                 diag_load<R>(wb, prof_t, sym);
                 step(wa);
                 if (s + 1 >= steps) break;
                 sym = dpp_row_shr1_or((dw >> 16) & 0xFFu, sym);
                 diag_load<R>(wa, prof_t, sym);
+                const uint32_t dn = gword[(s >> 2) + 1];
                 step(wb);
                 if (s + 2 >= steps) break;
                 sym = dpp_row_shr1_or(dw >> 24, sym);
