@@ -19,8 +19,10 @@
 //
 // One launch per class R (rows per lane, a multiple of 4): the class takes
 // the row lengths LA with 16(R-4) < LA <= 16R, and a workgroup takes a tile
-// (block pair r <= b) and a run of its row pairs of those lengths (they are
-// contiguous in the row-pair table).  1024 threads = 64 groups share one
+// (block pair r <= b) and a run of the block's row pairs of that class.  The
+// two row words of a pair are consecutive words of the class (their lengths
+// may differ: each half reads its score at its own row), so a block leaves at
+// most one half-empty pair per class.  1024 threads = 64 groups share one
 // similarity profile of the current row pair in LDS, laid out so that the 16
 // lanes of a group read 16 consecutive 16-byte units whatever symbols they
 // look up (the 64 LDS banks once each); symbols and profile entries are read
@@ -52,9 +54,6 @@ __host__ __device__ constexpr uint32_t diag_lds_bytes(int R, int alphabet, int C
 {
     return diag_prof_bytes(R, alphabet) + 2u * 2u * (uint32_t)CB * 2u + (uint32_t)kDiagGroups * kDiagBuf;
 }
-// Rows per lane of row length LA (1 <= LA <= 255): the smallest multiple of 4
-// whose 16 lanes cover LA rows.
-__host__ __device__ constexpr int diag_class(int LA) { return ((LA + 63) / 64) * 4; }
 
 __device__ __forceinline__ uint32_t dpp_row_shr1(uint32_t v)
 {
@@ -82,8 +81,8 @@ __device__ __forceinline__ void diag_load(u32x4 (&w)[R / 4], const uint32_t *pro
 
 template <int R>
 __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t idx_begin, uint64_t idx_end,
-                                                           void *out, int out_kind, EdgeSink E, int la_lo, int la_hi,
-                                                           uint32_t rb0, uint32_t rbn, uint32_t chunks, uint32_t rpc)
+                                                           void *out, int out_kind, EdgeSink E, uint32_t rb0,
+                                                           uint32_t rbn, uint32_t chunks, uint32_t rpc)
 {
     static_assert(R % 4 == 0 && R >= 4 && R <= 16, "rows per lane");
     extern __shared__ __align__(16) uint8_t lds[];
@@ -93,9 +92,9 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
 
     uint32_t r, b;
     if (!tile_block_pair(blockIdx.x / chunks, rb0, rbn, V.nb, r, b)) return;
-    // the row pairs of block r with lengths la_lo..la_hi, cut into runs of rpc
-    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1);
-    const uint32_t cbeg = rpo[la_lo], cend = rpo[la_hi + 1];
+    // the row pairs of block r in this class, cut into runs of rpc
+    const uint32_t *dpo = V.dp_off + (size_t)r * kDiagClasses + (R / 4 - 1);
+    const uint32_t cbeg = dpo[0], cend = dpo[1];
     const uint64_t pbeg64 = (uint64_t)cbeg + (uint64_t)(blockIdx.x % chunks) * rpc;
     if (pbeg64 >= cend) return;
     const uint32_t pbeg = (uint32_t)pbeg64;
@@ -135,43 +134,43 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
     for (uint32_t k = pbeg; k <= pend; ++k) {
         __syncthreads();   // the previous DP has finished with the profile and its staging rows
         if (k < pend) {
-            const int32_t a0 = V.rpairs[2 * k], a1 = V.rpairs[2 * k + 1];
-            const int LA = V.blen[a0];
+            const int32_t a0 = V.dpairs[2 * k], a1 = V.dpairs[2 * k + 1];
+            const int LA0 = V.blen[a0], LA1 = a1 >= 0 ? V.blen[a1] : 0;
             const uint8_t *su = V.bsym + (int64_t)a0 * V.WB;
             const uint8_t *su2 = V.bsym + (int64_t)(a1 >= 0 ? a1 : a0) * V.WB;
             for (int e = tid; e < (A + 1) * ROWS; e += kDiagThreads) {
                 const int c = e / ROWS, i = e - c * ROWS;
                 const int lt = i / R, ri = i - lt * R;
                 uint32_t val;
-                if (c == A)
+                if (c == A) {
                     val = kSentinelPair;
-                else if (i < LA)
-                    val = (uint32_t)V.wtab[(int)su[i] * A + c] | ((uint32_t)V.wtab[(int)su2[i] * A + c] << 16);
-                else
-                    val = 0;
+                } else {
+                    // rows past a word's length never reach its score row
+                    val = i < LA0 ? (uint32_t)V.wtab[(int)su[i] * A + c] : 0u;
+                    if (i < LA1) val |= (uint32_t)V.wtab[(int)su2[i] * A + c] << 16;
+                }
                 prof[c * S + (ri >> 2) * (4 * kDiagLanes) + lt * 4 + (ri & 3)] = val;
             }
         }
         if (k > pbeg) {
             const uint32_t kk = k - 1;
-            const int LA = V.blen[V.rpairs[2 * kk]];
             const int16_t *srow = stg + (size_t)(kk & 1) * 2 * CB;
             for (int h = 0; h < 2; ++h) {
-                const int32_t slot = V.rpairs[2 * kk + h];
+                const int32_t slot = V.dpairs[2 * kk + h];
                 if (slot < 0) continue;
                 const int64_t u = I0 + V.bcol[slot];
                 const int64_t jstart = (r == b) ? u + 1 : J0;
-                store_row<kDiagThreads>(V, u, LA, jstart, J1, srow + h * CB + (jstart - J0), idx_begin, idx_end,
-                                        out, out_kind, E);
+                store_row<kDiagThreads>(V, u, V.blen[slot], jstart, J1, srow + h * CB + (jstart - J0), idx_begin,
+                                        idx_end, out, out_kind, E);
             }
         }
         __syncthreads();
         if (k == pend) break;
 
-        const int32_t a1 = V.rpairs[2 * k + 1];
-        const int LA = V.blen[V.rpairs[2 * k]];
-        const int tstar = (LA - 1) / R;     // lane holding row LA
-        const int istar = (LA - 1) % R;
+        const int32_t a1 = V.dpairs[2 * k + 1];
+        const int LA0 = V.blen[V.dpairs[2 * k]], LA1 = a1 >= 0 ? V.blen[a1] : LA0;
+        const int tstar0 = (LA0 - 1) / R, istar0 = (LA0 - 1) % R;   // lane and register of row LA0
+        const int tstar1 = (LA1 - 1) / R, istar1 = (LA1 - 1) % R;
         int16_t *sdst = stg + (size_t)(k & 1) * 2 * CB;
         // Column words: chunk c holds the 64 slots c*64 .. c*64+63; the four
         // groups of a wavefront take 4 consecutive slots (similar lengths), and
@@ -241,15 +240,17 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
                 step(wb);
                 dw = dn;
             }
-            // row LA of the final column lives in lane tstar, register istar
-            h2 res = col[0];
+            // row LA of the final column lives in lane tstar, register istar (per half)
+            h2 res0 = col[0], res1 = col[0];
 #pragma unroll
-            for (int i = 1; i < R; ++i) res = (i == istar) ? col[i] : res;
+            for (int i = 1; i < R; ++i) {
+                res0 = (i == istar0) ? col[i] : res0;
+                res1 = (i == istar1) ? col[i] : res1;
+            }
             const int col_idx = V.bcol[slot];
-            if (t == tstar && col_idx != 0xFFFF) {
-                const int off = V.gap * (LA + lb);
-                sdst[col_idx] = (int16_t)((int)res[0] + off);
-                if (a1 >= 0) sdst[CB + col_idx] = (int16_t)((int)res[1] + off);
+            if (col_idx != 0xFFFF) {
+                if (t == tstar0) sdst[col_idx] = (int16_t)((int)res0[0] + V.gap * (LA0 + lb));
+                if (a1 >= 0 && t == tstar1) sdst[CB + col_idx] = (int16_t)((int)res1[1] + V.gap * (LA1 + lb));
             }
         }
     }

@@ -206,7 +206,6 @@ hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t
 
 // Row lengths of anti-diagonal class R (rows per lane): (16(R-4), 16R].
 static int diag_la_lo(int R) { return kDiagLanes * (R - 4) + 1; }
-static int diag_la_hi(int R) { return kDiagLanes * R; }
 
 bool diag_fits(const DevVocab &V)
 {
@@ -215,8 +214,9 @@ bool diag_fits(const DevVocab &V)
     return true;
 }
 
-hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
-                                int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E)
+hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, const uint32_t *h_maxdp,
+                                uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out, hipStream_t stream,
+                                const EdgeSink *E)
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     // a class whose profile does not fit in LDS (large alphabets with long
@@ -236,21 +236,19 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, uint
         hipError_t e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
         if (e != hipSuccess) return e;
     }
-    for (int R = 4; R <= 16; R += 4) {
-        int la_lo = diag_la_lo(R), la_hi = std::min(diag_la_hi(R), (int)V.lmax);
-        if (la_lo > la_hi) break;
-        uint64_t maxrp = 0;   // bound on the row pairs of one block in this class
-        for (int LA = la_lo; LA <= la_hi; ++LA) maxrp += h_maxrp[LA];
+    for (int c = 0; c < kDiagClasses; ++c) {
+        const int R = 4 * (c + 1);
+        const uint32_t maxrp = h_maxdp[c];   // most row pairs of this class in one block
         if (maxrp == 0) continue;
         // runs of row pairs so that a launch has about kDiagWorkgroups workgroups
         constexpr uint64_t kDiagWorkgroups = 2048;
         uint32_t chunks = (uint32_t)std::min<uint64_t>(maxrp, std::max<uint64_t>(1, (kDiagWorkgroups + G.blocks - 1) / G.blocks));
-        uint32_t rpc = (uint32_t)((maxrp + chunks - 1) / chunks);
+        uint32_t rpc = (maxrp + chunks - 1) / chunks;
         const void *fn = R == 4 ? reinterpret_cast<const void *>(&k_tri_diag<4>)
                        : R == 8 ? reinterpret_cast<const void *>(&k_tri_diag<8>)
                        : R == 12 ? reinterpret_cast<const void *>(&k_tri_diag<12>)
                                  : reinterpret_cast<const void *>(&k_tri_diag<16>);
-        void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &la_lo, &la_hi, &rb0, &rbn, &chunks, &rpc};
+        void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
         const size_t lds = diag_lds_bytes(R, V.alphabet, V.CB);
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;

@@ -65,7 +65,8 @@ constexpr int kPhasePeriod = 8;
 
 // Byte offsets of every region inside d_mem.
 struct Layout {
-    uint64_t csym, clen, bsym, blen, bcol, rpairs, rp_off, wtab, submat, borig, gpairs, gp_off, psym, plen, porig, total;
+    uint64_t csym, clen, bsym, blen, bcol, rpairs, rp_off, dpairs, dp_off, wtab, submat, borig, gpairs, gp_off, psym, plen,
+        porig, total;
     int CB, WB, nb;
     uint64_t nprobe, pslots;
 };
@@ -91,6 +92,9 @@ Layout make_layout(uint64_t n, uint32_t max_len)
     L.bcol = take(slots * 2);
     L.rpairs = take(slots * 2 * 4);
     L.rp_off = take(((uint64_t)L.nb * (std::max<uint32_t>(max_len, 1) + 1) + 1) * 4);
+    // at most one half-empty pair per block and class
+    L.dpairs = take((slots / 2 + (uint64_t)L.nb * kDiagClasses) * 2 * 4);
+    L.dp_off = take(((uint64_t)L.nb * kDiagClasses + 1) * 4);
     L.wtab = take(256 * 256 * 2);
     L.submat = take(256 * 256);
     L.borig = take(slots * 4);
@@ -280,7 +284,7 @@ hipError_t nw::host::launch_triangle(const nw_vocab *v, uint64_t idx_begin, uint
 {
     // words longer than the register-row limit take the anti-diagonal kernel
     const int kind = dt == NW_I8 ? OUT_I8 : OUT_I16;
-    return v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, v->h_maxrp.data(), idx_begin, idx_end, kind, d_out, stream)
+    return v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, v->h_maxrp.data(), v->h_maxdp, idx_begin, idx_end, kind, d_out, stream)
                                           : launch_triangle_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, kind, d_out, stream);
 }
 
@@ -379,6 +383,8 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     uint16_t *bcol = reinterpret_cast<uint16_t *>(img.data() + L.bcol);
     int32_t *rpairs = reinterpret_cast<int32_t *>(img.data() + L.rpairs);
     uint32_t *rp_off = reinterpret_cast<uint32_t *>(img.data() + L.rp_off);
+    int32_t *dpairs = reinterpret_cast<int32_t *>(img.data() + L.dpairs);
+    uint32_t *dp_off = reinterpret_cast<uint32_t *>(img.data() + L.dp_off);
     uint16_t *wtab = reinterpret_cast<uint16_t *>(img.data() + L.wtab);
     int8_t *submat = reinterpret_cast<int8_t *>(img.data() + L.submat);
 
@@ -388,7 +394,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
         if (l) std::memcpy(csym + i * L.WB, h_symbols + h_offsets[i], l);
     }
     const int LM = (int)max_len;
-    uint32_t npairs = 0;
+    uint32_t npairs = 0, ndpairs = 0;
     std::vector<std::vector<int>> by_len(LM + 1);
     for (int blk = 0; blk < L.nb; ++blk) {
         const uint64_t u0 = (uint64_t)blk * L.CB;
@@ -408,6 +414,28 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
                 slot_of[c] = s;
                 ++s;
             }
+        // anti-diagonal classes: consecutive slots of one class (ascending lengths)
+        for (int c = 0; c < kDiagClasses; ++c) {
+            dp_off[(size_t)blk * kDiagClasses + c] = ndpairs;
+            int32_t open = -1;
+            for (uint64_t q = u0; q < u0 + L.CB; ++q) {
+                const int l = blen[q];
+                if (l < 64 * c + 1 || l > 64 * c + 64) continue;
+                if (open < 0) {
+                    open = (int32_t)q;
+                } else {
+                    dpairs[2 * ndpairs] = open;
+                    dpairs[2 * ndpairs + 1] = (int32_t)q;
+                    ++ndpairs;
+                    open = -1;
+                }
+            }
+            if (open >= 0) {
+                dpairs[2 * ndpairs] = open;
+                dpairs[2 * ndpairs + 1] = -1;
+                ++ndpairs;
+            }
+        }
         for (int l = 0; l <= LM; ++l) {
             rp_off[(size_t)blk * (LM + 1) + l] = npairs;
             const auto &v = by_len[l];
@@ -419,6 +447,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
         }
     }
     rp_off[(size_t)L.nb * (LM + 1)] = npairs;
+    dp_off[(size_t)L.nb * kDiagClasses] = ndpairs;
     // the same row pairs grouped by length only
     std::vector<uint32_t> h_gp_off(kMaxLen + 2, 0);
     {
@@ -476,6 +505,8 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     D.bcol = reinterpret_cast<const uint16_t *>(base + L.bcol);
     D.rpairs = reinterpret_cast<const int32_t *>(base + L.rpairs);
     D.rp_off = reinterpret_cast<const uint32_t *>(base + L.rp_off);
+    D.dpairs = reinterpret_cast<const int32_t *>(base + L.dpairs);
+    D.dp_off = reinterpret_cast<const uint32_t *>(base + L.dp_off);
     D.wtab = reinterpret_cast<const uint16_t *>(base + L.wtab);
     D.submat = reinterpret_cast<const int8_t *>(base + L.submat);
     D.n = (int64_t)n;
@@ -508,6 +539,9 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
             const uint32_t c = rp_off[r * (LM + 1) + la + 1] - rp_off[r * (LM + 1) + la];
             v->h_maxrp[la] = std::max(v->h_maxrp[la], c);
         }
+    for (uint64_t r = 0; r < L.nb; ++r)
+        for (int c = 0; c < kDiagClasses; ++c)
+            v->h_maxdp[c] = std::max(v->h_maxdp[c], dp_off[r * kDiagClasses + c + 1] - dp_off[r * kDiagClasses + c]);
     v->smin = smin;
     v->smax = smax;
     v->n = n;
@@ -561,7 +595,7 @@ int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx
 {
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
     if (rc) return rc;
-    hipError_t e = launch_triangle_diag(v->dev, v->h_maxrp.data(), idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
+    hipError_t e = launch_triangle_diag(v->dev, v->h_maxrp.data(), v->h_maxdp, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
                                         (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the anti-diagonal triangle kernel");
     return ok();
@@ -610,7 +644,7 @@ int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, 
     E.lo = f->lo;
     E.hi = f->hi;
     E.den = f->mode == NW_EDGE_NORMALISED ? f->den : 1;
-    e = v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, v->h_maxrp.data(), idx_begin, idx_end, OUT_EDGES, nullptr, st, &E)
+    e = v->max_len > (uint32_t)kMaxLen ? launch_triangle_diag(v->dev, v->h_maxrp.data(), v->h_maxdp, idx_begin, idx_end, OUT_EDGES, nullptr, st, &E)
                                        : launch_edges_tiled(v->dev, v->h_maxrp.data(), idx_begin, idx_end, E, st);
     if (e != hipSuccess) return dev_fail(e, "launching the edge kernels");
     return ok();

@@ -14,6 +14,7 @@ namespace nw {
 // (up to kLongMaxLen) for the triangle calls.
 constexpr int kMaxLen = 48;
 constexpr int kLongMaxLen = 255;   // lengths are stored as uint8
+constexpr int kDiagClasses = 4;    // row-length classes of the anti-diagonal kernel (64 lengths each)
 // Threads per workgroup of the tiled kernels (four wave64 wavefronts).
 constexpr int kThreads = 256;
 // Bytes of a padded word in the blocked layout (kMaxLen symbols, whole 16-byte loads).
@@ -34,7 +35,10 @@ constexpr uint32_t kSentinelPair = 0xE800E800u;
 // Row pairs: for block r and length L, rpairs[rp_off[r*(LMAX+1)+L] .. rp_off[..+1])
 // lists pairs of sorted slots of that block whose words both have length L
 // (second slot -1 when the count is odd).  gpairs holds the same pairs grouped
-// by length only: gpairs[gp_off[L] .. gp_off[L+1]).
+// by length only: gpairs[gp_off[L] .. gp_off[L+1]).  dpairs pairs the words of
+// a block by class of the anti-diagonal kernel instead (class c: lengths
+// 64c+1 .. 64c+64), consecutive in slot order (so of similar lengths):
+// dpairs[dp_off[r*kDiagClasses + c] .. dp_off[r*kDiagClasses + c + 1]).
 // borig[s] is the caller index of slot s (-1 for padding slots).
 // Probe subset (threshold pre-pass of the top-k): nprobe words at caller
 // indices floor(i*n/nprobe), sorted by length, as a column set of pslots slots.
@@ -60,6 +64,8 @@ struct DevVocab {
     const int32_t *borig;       // [nb*CB]
     const int32_t *gpairs;      // [num_row_pairs][2]
     const uint32_t *gp_off;     // [kMaxLen+2]
+    const int32_t *dpairs;      // row pairs of the anti-diagonal classes, [.][2]
+    const uint32_t *dp_off;     // [nb*kDiagClasses+1]
     const uint8_t *psym;        // probe words [pslots*WB]
     const uint8_t *plen;        // [pslots]
     const int32_t *porig;       // [pslots]
@@ -106,8 +112,11 @@ hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64
 // launch per class of row lengths.  A dictionary whose longest words need a
 // profile larger than LDS (diag_fits false) is scored by the naive kernel.
 bool diag_fits(const DevVocab &V);
-hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
-                                int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E = nullptr);
+// h_maxrp[0] = most empty row pairs in one block; h_maxdp[c] = most row pairs
+// of class c in one block.
+hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, const uint32_t *h_maxdp,
+                                uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out, hipStream_t stream,
+                                const EdgeSink *E = nullptr);
 
 // Per-row top-k lists of the rows R (pairs grouped by length, h_off = host
 // copy of R.off) against the column set C, split over nsplit column ranges:
