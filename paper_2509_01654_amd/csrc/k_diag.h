@@ -17,16 +17,15 @@
 // hands them on, and lane 0 takes the next symbol of the word from an aligned
 // dword of LDS read once per four steps.
 //
-// One launch per class R (rows per lane, a multiple of 4): the class takes
-// the row lengths LA with 16(R-4) < LA <= 16R, and a workgroup takes a tile
+// One launch per class R (rows per lane, even): the class takes the row
+// lengths LA with 16(R-2) < LA <= 16R, and a workgroup takes a tile
 // (block pair r <= b) and a run of the block's row pairs of that class.  The
 // two row words of a pair are consecutive words of the class (their lengths
 // may differ: each half reads its score at its own row), so a block leaves at
 // most one half-empty pair per class.  1024 threads = 64 groups share one
-// similarity profile of the current row pair in LDS, laid out so that the 16
-// lanes of a group read 16 consecutive 16-byte units whatever symbols they
-// look up (the 64 LDS banks once each); symbols and profile entries are read
-// one step ahead of the DP.  The score of a pair is row LA of the final
+// similarity profile of the current row pair in LDS, laid out so that the
+// lanes' reads never meet in an LDS bank whatever symbols they look up (see
+// diag_load); profile entries are read one step ahead of the DP.  The score of a pair is row LA of the final
 // column.
 #pragma once
 
@@ -43,17 +42,22 @@ constexpr int kDiagBuf = 256 + 32;
 // Largest workgroup LDS of the device.
 constexpr uint32_t kDiagMaxLds = 160u * 1024u;
 
-// Dwords per profile row (one symbol): 16R, a multiple of 64 (R % 4 == 0).
-__host__ __device__ constexpr uint32_t diag_stride_dw(int R) { return (uint32_t)(kDiagLanes * R); }
+// Profile of a class with R rows per lane (R even, 2..16): the first R & ~3
+// rows of every lane in 16-byte units (main part), the last two rows of an
+// R = 4m+2 class in 8-byte units (tail).  Dwords per symbol:
+__host__ __device__ constexpr uint32_t diag_main_dw(int R) { return (uint32_t)(kDiagLanes * (R & ~3)); }
+__host__ __device__ constexpr uint32_t diag_tail_dw(int R) { return (R & 2) ? 4u * kDiagLanes : 0u; }
 __host__ __device__ constexpr uint32_t diag_prof_bytes(int R, int alphabet)
 {
-    return (uint32_t)(alphabet + 1) * diag_stride_dw(R) * 4u;
+    return (uint32_t)(alphabet + 1) * (diag_main_dw(R) + diag_tail_dw(R)) * 4u;
 }
 // LDS: one profile, two int16 staging row pairs, the group word buffers.
 __host__ __device__ constexpr uint32_t diag_lds_bytes(int R, int alphabet, int CB)
 {
     return diag_prof_bytes(R, alphabet) + 2u * 2u * (uint32_t)CB * 2u + (uint32_t)kDiagGroups * kDiagBuf;
 }
+// Row-length class c (0 <= c < kDiagClasses) takes lengths 32c+1 .. 32c+32 with R = 2(c+1).
+__host__ __device__ constexpr int diag_rows_per_lane(int c) { return 2 * (c + 1); }
 
 __device__ __forceinline__ uint32_t dpp_row_shr1(uint32_t v)
 {
@@ -66,14 +70,30 @@ __device__ __forceinline__ uint32_t dpp_row_shr1_or(uint32_t first, uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x111, 0xF, 0xF, false);
 }
 
-// Profile entry of lane t, its row q*4 + e (0 <= e < 4) within the lane, for
-// symbol c: dword c*16R + q*64 + t*4 + e.
+// Profile reads of one step.  Main part: the entry of lane t, its row 4q + e
+// (0 <= e < 4), symbol c, is dword c*16(R & ~3) + 64q + 4t + e, so the 16
+// lanes of a group read 16 consecutive 16-byte units (the 64 banks once) for
+// any symbols.  Tail (rows R-2, R-1): symbol c holds two copies of 32 dwords,
+// lane t's pair at 2t (+e); group g reads copy g & 1, so the two groups that
+// share an 8-byte read pass use opposite halves of the banks.
 template <int R>
-__device__ __forceinline__ void diag_load(u32x4 (&w)[R / 4], const uint32_t *prof_t, uint32_t sym)
+struct DiagW {
+    static constexpr int Q = R / 4;
+    u32x4 q[Q > 0 ? Q : 1];
+    uint2 tail;
+    __device__ __forceinline__ uint32_t operator[](int i) const
+    {
+        return i < 4 * Q ? q[i >> 2][i & 3] : (i - 4 * Q == 0 ? tail.x : tail.y);
+    }
+};
+
+template <int R>
+__device__ __forceinline__ void diag_load(DiagW<R> &w, const uint32_t *prof_t, const uint32_t *tail_t, uint32_t sym)
 {
-    const u32x4 *row = reinterpret_cast<const u32x4 *>(prof_t + sym * diag_stride_dw(R));
+    const u32x4 *row = reinterpret_cast<const u32x4 *>(prof_t + sym * diag_main_dw(R));
 #pragma unroll
-    for (int q = 0; q < R / 4; ++q) w[q] = row[q * kDiagLanes];
+    for (int q = 0; q < R / 4; ++q) w.q[q] = row[q * kDiagLanes];
+    if constexpr ((R & 2) != 0) w.tail = *reinterpret_cast<const uint2 *>(tail_t + sym * diag_tail_dw(R));
     // issue the reads here, one step before their use: keep the scheduler
     // from sinking them next to the DP that consumes them
     __builtin_amdgcn_sched_barrier(0);
@@ -84,16 +104,16 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
                                                            void *out, int out_kind, EdgeSink E, uint32_t rb0,
                                                            uint32_t rbn, uint32_t chunks, uint32_t rpc)
 {
-    static_assert(R % 4 == 0 && R >= 4 && R <= 16, "rows per lane");
+    static_assert(R % 2 == 0 && R >= 2 && R <= 16, "rows per lane");
     extern __shared__ __align__(16) uint8_t lds[];
-    constexpr uint32_t S = diag_stride_dw(R);
+    constexpr uint32_t SM = diag_main_dw(R), ST = diag_tail_dw(R);
     constexpr int ROWS = kDiagLanes * R;
-    constexpr int Q = R / 4;
+    constexpr int R4 = R & ~3;   // rows of a lane in the main part
 
     uint32_t r, b;
     if (!tile_block_pair(blockIdx.x / chunks, rb0, rbn, V.nb, r, b)) return;
     // the row pairs of block r in this class, cut into runs of rpc
-    const uint32_t *dpo = V.dp_off + (size_t)r * kDiagClasses + (R / 4 - 1);
+    const uint32_t *dpo = V.dp_off + (size_t)r * kDiagClasses + (R / 2 - 1);
     const uint32_t cbeg = dpo[0], cend = dpo[1];
     const uint64_t pbeg64 = (uint64_t)cbeg + (uint64_t)(blockIdx.x % chunks) * rpc;
     if (pbeg64 >= cend) return;
@@ -120,7 +140,9 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
     int16_t *stg = reinterpret_cast<int16_t *>(lds + diag_prof_bytes(R, A));   // [2][2][CB]
     uint8_t *gbuf_all = lds + diag_prof_bytes(R, A) + 2 * 2 * CB * 2;
     uint8_t *gbuf = gbuf_all + g * kDiagBuf;
+    uint32_t *ptail = prof + (size_t)(A + 1) * SM;
     const uint32_t *prof_t = prof + t * 4;
+    const uint32_t *tail_t = ptail + (g & 1) * (ST / 2) + 2 * t;
     const uint32_t *gword = reinterpret_cast<const uint32_t *>(gbuf);
     const int wq = V.WB / 16;               // 16-byte units of a padded word
 
@@ -149,7 +171,13 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
                     val = i < LA0 ? (uint32_t)V.wtab[(int)su[i] * A + c] : 0u;
                     if (i < LA1) val |= (uint32_t)V.wtab[(int)su2[i] * A + c] << 16;
                 }
-                prof[c * S + (ri >> 2) * (4 * kDiagLanes) + lt * 4 + (ri & 3)] = val;
+                if (ri < R4) {
+                    prof[c * SM + (ri >> 2) * (4 * kDiagLanes) + lt * 4 + (ri & 3)] = val;
+                } else {
+                    uint32_t *tp = ptail + c * ST + 2 * lt + (ri - R4);
+                    tp[0] = val;
+                    tp[ST / 2] = val;
+                }
             }
         }
         if (k > pbeg) {
@@ -196,14 +224,14 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
             uint32_t last = 0, diag_in = 0;
             // one step: row i takes its diagonal sum from the old value of row
             // i-1 before the max3 chain overwrites it, so the column updates in place
-            auto step = [&](const u32x4(&w)[Q]) __attribute__((always_inline)) {
+            auto step = [&](const DiagW<R> &w) __attribute__((always_inline)) {
                 const uint32_t up_in = dpp_row_shr1(last);
-                h2 a = as_h2(diag_in) + as_h2(w[0][0]);
+                h2 a = as_h2(diag_in) + as_h2(w[0]);
                 h2 up = as_h2(up_in);
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     h2 an = h2{0, 0};
-                    if (i + 1 < R) an = col[i] + as_h2(w[(i + 1) >> 2][(i + 1) & 3]);
+                    if (i + 1 < R) an = col[i] + as_h2(w[i + 1]);
                     col[i] = max3(a, col[i], up);
                     up = col[i];
                     a = an;
@@ -219,24 +247,24 @@ __global__ __launch_bounds__(kDiagThreads) void k_tri_diag(DevVocab V, uint64_t 
             const int steps = lbmax_w + kDiagLanes - 1;
             uint32_t dw = gword[0];
             uint32_t sym = t == 0 ? (dw & 0xFFu) : (uint32_t)A;
-            u32x4 wa[Q], wb[Q];
-            diag_load<R>(wa, prof_t, sym);
+            DiagW<R> wa, wb;
+            diag_load<R>(wa, prof_t, tail_t, sym);
             for (int s = 0; s < steps; s += 4) {
                 sym = dpp_row_shr1_or((dw >> 8) & 0xFFu, sym);
-                diag_load<R>(wb, prof_t, sym);
+                diag_load<R>(wb, prof_t, tail_t, sym);
                 step(wa);
                 if (s + 1 >= steps) break;
                 sym = dpp_row_shr1_or((dw >> 16) & 0xFFu, sym);
-                diag_load<R>(wa, prof_t, sym);
+                diag_load<R>(wa, prof_t, tail_t, sym);
                 const uint32_t dn = gword[(s >> 2) + 1];
                 step(wb);
                 if (s + 2 >= steps) break;
                 sym = dpp_row_shr1_or(dw >> 24, sym);
-                diag_load<R>(wb, prof_t, sym);
+                diag_load<R>(wb, prof_t, tail_t, sym);
                 step(wa);
                 if (s + 3 >= steps) break;
                 sym = dpp_row_shr1_or(dn & 0xFFu, sym);
-                diag_load<R>(wa, prof_t, sym);
+                diag_load<R>(wa, prof_t, tail_t, sym);
                 step(wb);
                 dw = dn;
             }

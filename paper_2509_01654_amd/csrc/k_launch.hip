@@ -204,13 +204,10 @@ hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t
     return hipGetLastError();
 }
 
-// Row lengths of anti-diagonal class R (rows per lane): (16(R-4), 16R].
-static int diag_la_lo(int R) { return kDiagLanes * (R - 4) + 1; }
-
 bool diag_fits(const DevVocab &V)
 {
-    for (int R = 4; R <= 16; R += 4)
-        if (diag_la_lo(R) <= V.lmax && diag_lds_bytes(R, V.alphabet, V.CB) > kDiagMaxLds) return false;
+    for (int c = 0; c < kDiagClasses; ++c)
+        if (32 * c + 1 <= V.lmax && diag_lds_bytes(diag_rows_per_lane(c), V.alphabet, V.CB) > kDiagMaxLds) return false;
     return true;
 }
 
@@ -237,17 +234,19 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
         if (e != hipSuccess) return e;
     }
     for (int c = 0; c < kDiagClasses; ++c) {
-        const int R = 4 * (c + 1);
+        const int R = diag_rows_per_lane(c);
         const uint32_t maxrp = h_maxdp[c];   // most row pairs of this class in one block
         if (maxrp == 0) continue;
         // runs of row pairs so that a launch has about kDiagWorkgroups workgroups
         constexpr uint64_t kDiagWorkgroups = 2048;
         uint32_t chunks = (uint32_t)std::min<uint64_t>(maxrp, std::max<uint64_t>(1, (kDiagWorkgroups + G.blocks - 1) / G.blocks));
         uint32_t rpc = (maxrp + chunks - 1) / chunks;
-        const void *fn = R == 4 ? reinterpret_cast<const void *>(&k_tri_diag<4>)
-                       : R == 8 ? reinterpret_cast<const void *>(&k_tri_diag<8>)
-                       : R == 12 ? reinterpret_cast<const void *>(&k_tri_diag<12>)
-                                 : reinterpret_cast<const void *>(&k_tri_diag<16>);
+        static const void *const kDiag[kDiagClasses] = {
+            reinterpret_cast<const void *>(&k_tri_diag<2>),  reinterpret_cast<const void *>(&k_tri_diag<4>),
+            reinterpret_cast<const void *>(&k_tri_diag<6>),  reinterpret_cast<const void *>(&k_tri_diag<8>),
+            reinterpret_cast<const void *>(&k_tri_diag<10>), reinterpret_cast<const void *>(&k_tri_diag<12>),
+            reinterpret_cast<const void *>(&k_tri_diag<14>), reinterpret_cast<const void *>(&k_tri_diag<16>)};
+        const void *fn = kDiag[c];
         void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
         const size_t lds = diag_lds_bytes(R, V.alphabet, V.CB);
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -420,7 +420,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
             int32_t open = -1;
             for (uint64_t q = u0; q < u0 + L.CB; ++q) {
                 const int l = blen[q];
-                if (l < 64 * c + 1 || l > 64 * c + 64) continue;
+                if (l < 32 * c + 1 || l > 32 * c + 32) continue;
                 if (open < 0) {
                     open = (int32_t)q;
                 } else {

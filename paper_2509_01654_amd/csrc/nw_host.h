@@ -20,7 +20,7 @@ struct nw_vocab {
     std::vector<uint8_t> h_clen;
     std::vector<uint32_t> h_rp_off;   // host copy of dev.rp_off
     std::vector<uint32_t> h_maxrp;    // per row length: most row pairs of that length in one block
-    uint32_t h_maxdp[nw::kDiagClasses] = {0, 0, 0, 0};   // per anti-diagonal class: most row pairs in one block
+    uint32_t h_maxdp[nw::kDiagClasses] = {};   // per anti-diagonal class: most row pairs in one block
     int32_t smin = 0, smax = 0;       // similarity extremes
     // phase timing of the last top-k call (HIP events on the caller's stream)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

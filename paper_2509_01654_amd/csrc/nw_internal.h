@@ -14,7 +14,7 @@ namespace nw {
 // (up to kLongMaxLen) for the triangle calls.
 constexpr int kMaxLen = 48;
 constexpr int kLongMaxLen = 255;   // lengths are stored as uint8
-constexpr int kDiagClasses = 4;    // row-length classes of the anti-diagonal kernel (64 lengths each)
+constexpr int kDiagClasses = 8;    // row-length classes of the anti-diagonal kernel (32 lengths each)
 // Threads per workgroup of the tiled kernels (four wave64 wavefronts).
 constexpr int kThreads = 256;
 // Bytes of a padded word in the blocked layout (kMaxLen symbols, whole 16-byte loads).
@@ -37,7 +37,7 @@ constexpr uint32_t kSentinelPair = 0xE800E800u;
 // (second slot -1 when the count is odd).  gpairs holds the same pairs grouped
 // by length only: gpairs[gp_off[L] .. gp_off[L+1]).  dpairs pairs the words of
 // a block by class of the anti-diagonal kernel instead (class c: lengths
-// 64c+1 .. 64c+64), consecutive in slot order (so of similar lengths):
+// 32c+1 .. 32c+32), consecutive in slot order (so of similar lengths):
 // dpairs[dp_off[r*kDiagClasses + c] .. dp_off[r*kDiagClasses + c + 1]).
 // borig[s] is the caller index of slot s (-1 for padding slots).
 // Probe subset (threshold pre-pass of the top-k): nprobe words at caller
