@@ -119,7 +119,10 @@ int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end,
  * per pair walk the score matrix by anti-diagonals (the stencil
  * parallelisation the paper proposes in Section 6).  nw_all_pairs_scores uses
  * it by itself for words longer than 48; this entry point forces it (for
- * comparison with the register-row kernel).  Same arguments and errors. */
+ * comparison with the register-row kernel).  A dictionary whose longest words
+ * need a similarity profile larger than LDS (e.g. more than 125 symbols with
+ * words over 192) is scored by the one-thread-per-pair kernel instead.  Same
+ * arguments and errors. */
 int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
                              void *d_out, void *hip_stream);
 
