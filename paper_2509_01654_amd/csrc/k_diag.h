@@ -39,8 +39,6 @@ constexpr int kDiagGroups = kDiagThreads / kDiagLanes;  // column words in fligh
 constexpr int kDiagMaxLen = 255;                        // longest word of the anti-diagonal path
 // Group word buffer: the padded word (at most 256 bytes) | 32 sentinels.
 constexpr int kDiagBuf = 256 + 32;
-// Largest workgroup LDS of the device.
-constexpr uint32_t kDiagMaxLds = 160u * 1024u;
 
 // Profile of a class with R rows per lane (R even, 2..16): the first R & ~3
 // rows of every lane in 16-byte units (main part), the last two rows of an

@@ -207,7 +207,7 @@ hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t
 bool diag_fits(const DevVocab &V)
 {
     for (int c = 0; c < kDiagClasses; ++c)
-        if (32 * c + 1 <= V.lmax && diag_lds_bytes(diag_rows_per_lane(c), V.alphabet, V.CB) > kDiagMaxLds) return false;
+        if (32 * c + 1 <= V.lmax && diag_lds_bytes(diag_rows_per_lane(c), V.alphabet, V.CB) > kMaxLdsBytes) return false;
     return true;
 }
 
@@ -305,9 +305,13 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
     for (int LA = 0; LA <= V.lmax; ++LA) {
         DevVocab Vc = V;
         TopkArgs Tc = T;
+        // the histogram copies go to LDS when they fit beside the profiles
+        // (large alphabets with wide score ranges add to global bins instead)
+        Tc.hist_in_lds = T.hist != nullptr && T.nbins <= kLdsHistMax &&
+                         topk_lds_bytes(LA, V.alphabet, T.nbins, 1, V.CB) <= kMaxLdsBytes;
         void *args[] = {&Vc, &Tc};
-        hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs), topk_lds_bytes(LA, V.alphabet, T.nbins, V.CB),
-                                  stream, args);
+        hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs),
+                                  topk_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), stream, args);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -27,6 +27,7 @@ struct TopkArgs {
     unsigned long long *hist;   // [nbins] or NULL
     int lo;                     // lowest score (key and bin origin)
     int nbins;
+    int hist_in_lds;            // 1: per-workgroup LDS histogram copies; 0: global atomics
     // block pairs of this launch: (b - r) mod phase_mod in [phase_lo, phase_hi]
     int phase_mod, phase_lo, phase_hi;
 };
@@ -41,9 +42,9 @@ constexpr int kHistCopies = 16;
 constexpr int kLdsHistMax = 1024;
 
 __host__ __device__ constexpr uint32_t hist_stride(int nbins) { return (uint32_t)(nbins | 1); }
-__host__ __device__ constexpr uint32_t topk_hist_bytes(int nbins)
+__host__ __device__ constexpr uint32_t topk_hist_bytes(int nbins, int in_lds)
 {
-    return nbins <= kLdsHistMax ? 4u * kHistCopies * hist_stride(nbins) : 0u;
+    return in_lds ? 4u * kHistCopies * hist_stride(nbins) : 0u;
 }
 // Candidates are first appended to one of two LDS pools (by row-pair parity)
 // and moved to the global lists between row pairs, many at a time, so the DP
@@ -56,9 +57,10 @@ constexpr int kPoolFlush = 48;     // a pool is flushed once it holds this many
 // metadata (length, column, threshold score; 8 bytes per slot), and the two
 // candidate pools (keys, words, counters).
 __host__ __device__ constexpr uint32_t topk_pool_bytes() { return 2u * kPool * 12u + 16u; }
-__host__ __device__ constexpr uint32_t topk_lds_bytes(int LA, int alphabet, int nbins, int CB)
+__host__ __device__ constexpr uint32_t topk_lds_bytes(int LA, int alphabet, int nbins, int hist_in_lds, int CB)
 {
-    return 2u * profile_bytes(LA, alphabet) + topk_hist_bytes(nbins) + 8u * (uint32_t)CB + topk_pool_bytes();
+    return 2u * profile_bytes(LA, alphabet) + topk_hist_bytes(nbins, hist_in_lds) + 8u * (uint32_t)CB +
+           topk_pool_bytes();
 }
 
 __device__ __forceinline__ void emit_candidate(const TopkArgs &T, int64_t w, uint64_t key)
@@ -128,7 +130,7 @@ void k_topk_tiled(DevVocab V, TopkArgs T)
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const uint32_t prof_bytes = profile_bytes(LA, V.alphabet);
-    const bool lds_hist = T.hist != nullptr && T.nbins <= kLdsHistMax;
+    const bool lds_hist = T.hist != nullptr && T.hist_in_lds;
     const uint32_t hs = hist_stride(T.nbins);
     uint32_t *hist_all = reinterpret_cast<uint32_t *>(lds + 2 * prof_bytes);
     // this lane's copy, indexed by the score itself (biased by lo)
@@ -139,10 +141,10 @@ void k_topk_tiled(DevVocab V, TopkArgs T)
     // The column block's slots are the same for every row pair: stage their
     // metadata once -- x = column | length << 16, y = score of the column
     // word's threshold (a pair can only enter that word's list at or above it)
-    uint2 *meta = reinterpret_cast<uint2 *>(lds + 2 * prof_bytes + topk_hist_bytes(T.nbins));
+    uint2 *meta = reinterpret_cast<uint2 *>(lds + 2 * prof_bytes + topk_hist_bytes(T.nbins, lds_hist));
     CandPool pool;
     {
-        uint8_t *pb = lds + 2 * prof_bytes + topk_hist_bytes(T.nbins) + 8u * (uint32_t)CB;
+        uint8_t *pb = lds + 2 * prof_bytes + topk_hist_bytes(T.nbins, lds_hist) + 8u * (uint32_t)CB;
         pool.key = reinterpret_cast<uint64_t *>(pb);
         pool.word = reinterpret_cast<int32_t *>(pb + 2 * kPool * 8);
         pool.n = reinterpret_cast<uint32_t *>(pb + 2 * kPool * 12);

@@ -14,6 +14,7 @@ namespace nw {
 // (up to kLongMaxLen) for the triangle calls.
 constexpr int kMaxLen = 48;
 constexpr int kLongMaxLen = 255;   // lengths are stored as uint8
+constexpr uint32_t kMaxLdsBytes = 160u * 1024u;   // LDS of one workgroup (and of one CU)
 constexpr int kDiagClasses = 8;    // row-length classes of the anti-diagonal kernel (32 lengths each)
 // Threads per workgroup of the tiled kernels (four wave64 wavefronts).
 constexpr int kThreads = 256;
