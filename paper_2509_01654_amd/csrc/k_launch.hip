@@ -6,6 +6,7 @@
 // row of the score matrix instead of the whole matrix).
 #define NW_LAUNCH_TU 1
 #include <algorithm>
+#include <mutex>
 
 #include "k_batch.h"
 #include "k_diag.h"
@@ -86,6 +87,90 @@ const KernelTables &kernel_tables()
     return t;
 }
 
+// Independent launches (the per-length launches of one call, which write
+// disjoint outputs or commute through atomics) spread over the caller's
+// stream and kForkStreams library streams of the current device, so that the
+// tail of one launch overlaps the start of the next.  The library streams
+// first wait for the caller's work so far; the caller's stream then waits for
+// theirs, so the call stays ordered on the caller's stream.  The library
+// streams are created once per device and kept for the process.
+#ifndef NW_FORK_STREAMS
+#define NW_FORK_STREAMS 3
+#endif
+constexpr int kForkStreams = NW_FORK_STREAMS;
+
+class StreamFork {
+  public:
+    explicit StreamFork(hipStream_t caller) : caller_(caller) {}
+    StreamFork(const StreamFork &) = delete;
+    StreamFork &operator=(const StreamFork &) = delete;
+    ~StreamFork()
+    {
+        if (begun_ && !ended_) (void)end();   // an error path still joins what was launched
+        for (hipEvent_t &e : done_)
+            if (e) hipEventDestroy(e);
+        if (start_) hipEventDestroy(start_);
+    }
+    // every launch after begin() goes to next()
+    hipError_t begin()
+    {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if ((e = library_streams(dev, lib_)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&start_, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventRecord(start_, caller_)) != hipSuccess) return e;
+        for (int i = 0; i < kForkStreams; ++i)
+            if ((e = hipStreamWaitEvent(lib_[i], start_, 0)) != hipSuccess) return e;
+        begun_ = true;
+        return hipSuccess;
+    }
+    hipStream_t next()
+    {
+        if (!begun_) return caller_;
+        const int i = turn_++ % (kForkStreams + 1);
+        used_[i] = true;
+        return i == 0 ? caller_ : lib_[i - 1];
+    }
+    // the caller's stream waits for every library stream that took a launch
+    hipError_t end()
+    {
+        ended_ = true;
+        for (int i = 0; i < kForkStreams; ++i) {
+            if (!used_[i + 1]) continue;
+            hipError_t e = hipEventCreateWithFlags(&done_[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(done_[i], lib_[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(caller_, done_[i], 0);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+
+  private:
+    static hipError_t library_streams(int dev, hipStream_t (&out)[kForkStreams])
+    {
+        static std::mutex mu;
+        static hipStream_t streams[64][kForkStreams] = {};
+        if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+        std::lock_guard<std::mutex> lock(mu);
+        for (int i = 0; i < kForkStreams; ++i) {
+            if (!streams[dev][i]) {
+                hipError_t e = hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking);
+                if (e != hipSuccess) return e;
+            }
+            out[i] = streams[dev][i];
+        }
+        return hipSuccess;
+    }
+    hipStream_t caller_;
+    hipStream_t lib_[kForkStreams] = {};
+    hipEvent_t start_ = nullptr;
+    hipEvent_t done_[kForkStreams] = {};
+    bool used_[kForkStreams + 1] = {};
+    bool begun_ = false, ended_ = false;
+    int turn_ = 0;
+};
+
 static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, hipStream_t stream, void **args)
 {
     if (lds > 65536) {
@@ -145,6 +230,9 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
+    StreamFork fork(stream);
+    hipError_t ef = fork.begin();
+    if (ef != hipSuccess) return ef;
     for (int LA = 0; LA <= V.lmax; ++LA) {
         if (h_maxrp[LA] == 0) continue;   // no block has row pairs of this length
         uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);
@@ -157,10 +245,10 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
         uint32_t rb0 = G.rb0, rbn = G.rbn;
         void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
         hipError_t e = launch_dyn(tab.tri[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
-                                  tri_lds_bytes(LA, V.alphabet, V.CB), stream, args);
+                                  tri_lds_bytes(LA, V.alphabet, V.CB), fork.next(), args);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return fork.end();
 }
 
 hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
@@ -169,6 +257,9 @@ hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
+    StreamFork fork(stream);
+    hipError_t ef = fork.begin();
+    if (ef != hipSuccess) return ef;
     for (int LA = 0; LA <= V.lmax; ++LA) {
         if (h_maxrp[LA] == 0) continue;
         uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);
@@ -179,10 +270,10 @@ hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64
         uint32_t rb0 = G.rb0, rbn = G.rbn;
         void *args[] = {&Vc, &Ec, &ib, &ie, &rb0, &rbn, &chunks, &rpc};
         hipError_t e = launch_dyn(tab.edges[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
-                                  edges_lds_bytes(LA, V.alphabet, V.CB), stream, args);
+                                  edges_lds_bytes(LA, V.alphabet, V.CB), fork.next(), args);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return fork.end();
 }
 
 hipError_t launch_triangle_naive(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out,
@@ -221,6 +312,9 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
     if (!diag_fits(V)) return launch_triangle_naive(V, idx_begin, idx_end, out_kind, d_out, stream, E);
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
+    StreamFork fork(stream);
+    hipError_t ef = fork.begin();
+    if (ef != hipSuccess) return ef;
     DevVocab Vc = V;
     uint64_t ib = idx_begin, ie = idx_end;
     void *po = d_out;
@@ -230,7 +324,7 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
     if (h_maxrp[0] != 0) {   // empty row words: score gap * lb, the register-row kernel of length 0
         uint32_t one = 1, all = 0xFFFFFFFFu;
         void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &one, &all};
-        hipError_t e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), stream, args);
+        hipError_t e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), fork.next(), args);
         if (e != hipSuccess) return e;
     }
     for (int c = 0; c < kDiagClasses; ++c) {
@@ -251,16 +345,22 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
         const size_t lds = diag_lds_bytes(R, V.alphabet, V.CB);
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        e = hipLaunchKernel(fn, dim3((uint32_t)((uint64_t)G.blocks * chunks)), dim3(kDiagThreads), args, lds, stream);
+        e = hipLaunchKernel(fn, dim3((uint32_t)((uint64_t)G.blocks * chunks)), dim3(kDiagThreads), args, lds,
+                            fork.next());
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return fork.end();
 }
 
 hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_off, const ColSet &C, int k,
-                        int nsplit, uint64_t *partial, hipStream_t stream)
+                        int nsplit, uint64_t *partial, hipStream_t stream, bool fork_streams)
 {
     const KernelTables &tab = kernel_tables();
+    StreamFork fork(stream);
+    if (fork_streams) {
+        hipError_t ef = fork.begin();
+        if (ef != hipSuccess) return ef;
+    }
     int64_t per = (C.nslots + nsplit - 1) / nsplit;
     per = (per + kThreads - 1) / kThreads * kThreads;
     const int rpw = 4;
@@ -281,10 +381,10 @@ hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_of
         Q.partial = partial;
         void *args[] = {&Q};
         const dim3 grid((np + rpw - 1) / rpw, nsplit);
-        hipError_t e = launch_dyn(tab.query[LA], grid, query_lds_bytes(LA, V.alphabet), stream, args);
+        hipError_t e = launch_dyn(tab.query[LA], grid, query_lds_bytes(LA, V.alphabet), fork.next(), args);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return fork_streams ? fork.end() : hipSuccess;
 }
 
 hipError_t launch_merge(const uint64_t *partial, int P, int kin, int64_t rows, int kout, int lo, int16_t *score,
@@ -302,6 +402,9 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
     if (V.n < 2) return hipSuccess;
     const uint32_t nblk_pairs = (uint32_t)((uint64_t)V.nb * (V.nb + 1) / 2);
     const KernelTables &tab = kernel_tables();
+    StreamFork fork(stream);
+    hipError_t ef = fork.begin();
+    if (ef != hipSuccess) return ef;
     for (int LA = 0; LA <= V.lmax; ++LA) {
         DevVocab Vc = V;
         TopkArgs Tc = T;
@@ -311,10 +414,10 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
                          topk_lds_bytes(LA, V.alphabet, T.nbins, 1, V.CB) <= kMaxLdsBytes;
         void *args[] = {&Vc, &Tc};
         hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs),
-                                  topk_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), stream, args);
+                                  topk_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), fork.next(), args);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return fork.end();
 }
 
 __global__ void k_scatter_lists(const int16_t *qs, const int32_t *qi, const int32_t *words, uint32_t B, int kq, int k,

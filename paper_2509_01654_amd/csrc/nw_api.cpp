@@ -704,7 +704,7 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     P.len = D.plen;
     P.orig = D.porig;
     P.nslots = D.pslots;
-    if ((e = launch_query(D, R, v->h_gp_off.data(), P, (int)k + 1, 1, partial, st)) != hipSuccess)
+    if ((e = launch_query(D, R, v->h_gp_off.data(), P, (int)k + 1, 1, partial, st, true)) != hipSuccess)
         return dev_fail(e, "launching the threshold pre-pass");
     if ((e = launch_merge(partial, 4, (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
         return dev_fail(e, "launching the threshold merge");

@@ -95,7 +95,10 @@ struct EdgeSink {
 };
 
 // Launchers.  Each enqueues on `stream` and returns the hipError_t of the
-// launches.
+// launches.  Launchers with one launch per row length (or class) spread those
+// independent launches over `stream` and three library streams of the device,
+// forked from `stream` and joined back into it with events, so the work is
+// still ordered on `stream` for the caller.
 
 // Triangle scores of pair indices [idx_begin, idx_end); with out_kind ==
 // OUT_EDGES the pairs of that range go to the edge sink E instead of d_out.
@@ -121,9 +124,11 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
 
 // Per-row top-k lists of the rows R (pairs grouped by length, h_off = host
 // copy of R.off) against the column set C, split over nsplit column ranges:
-// partial[row][nsplit*4][k].  Scoring from V.
+// partial[row][nsplit*4][k].  Scoring from V.  fork_streams spreads the
+// per-length launches over library streams (throughput calls; latency-bound
+// callers such as the server keep them on `stream`).
 hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_off, const ColSet &C, int k,
-                        int nsplit, uint64_t *partial, hipStream_t stream);
+                        int nsplit, uint64_t *partial, hipStream_t stream, bool fork_streams = false);
 
 // Merge partial lists [rows][P][kin] into the top kout (scores/indices
 // and/or the key of rank `rank`).
