@@ -297,7 +297,7 @@ def bench_edges(args, nw, synth, torch, dev):
             "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2),
                          "peak": round(PEAK_16BIT_OPS / 1e12, 2), "unit": "Tops/s (16-bit)",
                          "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
-                         "kernel": "k_tri_tiled (edge mode, every LA)",
+                         "kernel": "k_edges_tiled (every LA)",
                          "issue_frac": round(cells / (ms / 1e3) / PEAK_ISSUE_CELLS, 4)}}
 
 
