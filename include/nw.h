@@ -88,6 +88,11 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
                   const nw_scoring *sc, void *d_mem, uint64_t d_bytes, void *hip_stream,
                   nw_vocab **out);
 
+/* Every later call on this handle runs on the device that was current at
+ * nw_load_vocab: the library makes it current for the call and restores the
+ * caller's device before returning.  Streams and buffers passed with the
+ * handle must belong to that device. */
+
 /* Release the host descriptor (d_mem stays owned by the caller). */
 void nw_free_vocab(nw_vocab *v);
 

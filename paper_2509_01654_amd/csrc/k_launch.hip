@@ -93,7 +93,10 @@ const KernelTables &kernel_tables()
 // tail of one launch overlaps the start of the next.  The library streams
 // first wait for the caller's work so far; the caller's stream then waits for
 // theirs, so the call stays ordered on the caller's stream.  The library
-// streams are created once per device and kept for the process.
+// streams are created once per device and kept for the process; calls from
+// several host threads share them, which can serialize those calls against
+// each other but cannot deadlock: every wait binds to an event already
+// recorded, so each dependency points to work enqueued earlier.
 #ifndef NW_FORK_STREAMS
 #define NW_FORK_STREAMS 3
 #endif

@@ -584,6 +584,7 @@ int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end,
 {
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
     if (rc) return rc;
+    DeviceScope scope(v->device);
     hipError_t e = launch_triangle(v, idx_begin, idx_end, dt, d_out, (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the triangle kernels");
     return ok();
@@ -595,6 +596,7 @@ int nw_all_pairs_scores_diag(const nw_vocab *v, uint64_t idx_begin, uint64_t idx
 {
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
     if (rc) return rc;
+    DeviceScope scope(v->device);
     hipError_t e = launch_triangle_diag(v->dev, v->h_maxrp.data(), v->h_maxdp, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
                                         (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the anti-diagonal triangle kernel");
@@ -606,6 +608,7 @@ int nw_all_pairs_scores_naive(const nw_vocab *v, uint64_t idx_begin, uint64_t id
 {
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_out);
     if (rc) return rc;
+    DeviceScope scope(v->device);
     hipError_t e = launch_triangle_naive(v->dev, idx_begin, idx_end, dt == NW_I8 ? OUT_I8 : OUT_I16, d_out,
                                          (hipStream_t)hip_stream);
     if (e != hipSuccess) return dev_fail(e, "launching the naive triangle kernel");
@@ -626,6 +629,7 @@ int nw_all_pairs_edges(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, 
     if (cap > 0 && (!d_i || !d_j || !d_score)) return fail(NW_EINVAL, "NULL edge array with cap > 0");
     if (((uintptr_t)d_count & 7) || ((uintptr_t)d_i & 3) || ((uintptr_t)d_j & 3) || ((uintptr_t)d_score & 1))
         return fail(NW_EINVAL, "misaligned edge count or edge arrays");
+    DeviceScope scope(v->device);
     if (idx_begin > idx_end || idx_end > v->num_pairs)
         return fail(NW_EINVAL, "pair range [%llu, %llu) outside [0, %llu]", (unsigned long long)idx_begin,
                     (unsigned long long)idx_end, (unsigned long long)v->num_pairs);
@@ -663,6 +667,7 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
                       uint64_t ws_bytes, void *hip_stream)
 {
     if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    DeviceScope scope(v->device);
     if (k < 1 || k > 63) return fail(NW_EINVAL, "k = %u outside 1..63", k);
     if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
     if (v->max_len > (uint32_t)kMaxLen)
@@ -823,6 +828,7 @@ int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_
              int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes, void *hip_stream)
 {
     if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    DeviceScope scope(v->device);
     if (k < 1 || k > 64) return fail(NW_EINVAL, "k = %u outside 1..64", k);
     if (n_q == 0) return ok();
     if (!h_q_offsets || !d_score || !d_index) return fail(NW_EINVAL, "NULL argument");

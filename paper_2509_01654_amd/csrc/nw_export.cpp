@@ -49,6 +49,7 @@ int nw_export_triangle(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, 
     int rc = check_triangle_args(v, idx_begin, idx_end, dt, d_ws);
     if (rc) return rc;
     if (idx_end == idx_begin) return ok();
+    DeviceScope scope(v->device);
     if (!fn || !h_buf) return fail(NW_EINVAL, "NULL callback or host buffer");
     if (chunk_pairs == 0) return fail(NW_EINVAL, "chunk_pairs must be at least 1");
     if ((uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be 256-byte aligned");

@@ -12,6 +12,22 @@
 #include "../../include/nw.h"
 #include "nw_internal.h"
 
+// Makes `dev` current for the scope and restores the caller's device after.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess) prev = cur;
+    }
+    ~DeviceScope()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    DeviceScope(const DeviceScope &) = delete;
+    DeviceScope &operator=(const DeviceScope &) = delete;
+};
+
 // Host descriptor of a loaded dictionary (the opaque nw_vocab of nw.h).
 struct nw_vocab {
     nw::DevVocab dev;
