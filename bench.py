@@ -72,6 +72,23 @@ def counter_traffic():
     return float(fields["fetch_bytes"]), float(fields["write_bytes"])
 
 
+def measured_packed_peak(nw, torch, blocks=2048, trips=4096, runs=3):
+    """The packed lane-instruction rate the chip sustains during this run:
+    nw_packed_issue_rate's launch (the DP's add + max3 pair, independent
+    chains, every CU at full occupancy) timed with events on the current
+    stream; the best of `runs` after one warm-up launch."""
+    nw.packed_issue_rate(blocks, trips)
+    best = 0.0
+    for _ in range(runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        n_instr = nw.packed_issue_rate(blocks, trips)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, n_instr / (e0.elapsed_time(e1) / 1e3))
+    return best
+
+
 def counter_issue():
     """VALU and LDS figures of the main pass from the same summary (same gate)."""
     fields = _summary_fields("counters:")
@@ -456,6 +473,13 @@ def main():
                            "traffic": None if tr is None else round(tr[0] + tr[1]),
                            "kernel": "k_topk_tiled (all-pairs main pass, every LA)",
                            "issue_frac": round(cells / (main_ms / 1e3) / PEAK_ISSUE_CELLS, 4)}
+        rate = measured_packed_peak(nw, torch)
+        rec["roofline"]["measured_peak"] = {
+            "kernel": "k_packed_rate (nw_packed_issue_rate: the DP's packed add + max3, independent chains)",
+            "packed_lane_instr_per_s": round(rate / 1e12, 2), "unit": "10^12 per s",
+            "ops_16bit_per_s": round(2 * rate / 1e12, 2),
+            "frac": round(achieved / (2 * rate), 4),
+            "issue_frac": round(cells / (main_ms / 1e3) / rate, 4)}
         iss = counter_issue()
         if iss is not None:
             rec["roofline"]["counters"] = iss

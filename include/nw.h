@@ -378,6 +378,18 @@ int nw_graph_csr(uint64_t n, const int32_t *d_i, const int32_t *d_j, uint64_t m,
 int nw_ego_network(uint64_t n, const int64_t *d_row_ptr, const int32_t *d_adj, const int32_t *h_seeds,
                    uint32_t n_seeds, uint32_t depth, int32_t *d_dist, void *hip_stream);
 
+/* Issue-rate microbenchmark of the DP's instruction pair (one packed add and
+ * one packed three-input max per two cells): `blocks` workgroups of 256
+ * threads each issue trips x 64 packed instructions in eight independent
+ * chains per lane, touching no memory.  Enqueued on hip_stream; the caller
+ * times it (events on that stream).  *lane_instructions receives the number
+ * of lane-instructions the launch issues, so instructions per second is the
+ * packed issue rate the chip sustains at its running clock, and twice that
+ * the 16-bit operation rate (two halves per instruction): the measured
+ * counterpart of the nominal 256 CUs x 64 lanes x clock.  Errors: NW_EINVAL
+ * (blocks or trips 0, NULL out), NW_EDEVICE. */
+int nw_packed_issue_rate(uint32_t blocks, uint32_t trips, uint64_t *lane_instructions, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "nw_all_pairs_edges": (ctypes.c_int, [P, u64, u64, ctypes.POINTER(_EdgeFilter), P, P, P, u64, P, P]),
         "nw_export_triangle": (ctypes.c_int, [P, u64, u64, ctypes.c_int, u64, P, P, _CHUNK_FN, P, P]),
         "nw_graph_workspace_bytes": (ctypes.c_int, [u64, ctypes.POINTER(u64)]),
+        "nw_packed_issue_rate": (ctypes.c_int, [u32, u32, ctypes.POINTER(u64), P]),
         "nw_graph_csr": (ctypes.c_int, [u64, P, P, u64, P, P, P, u64, P]),
         "nw_ego_network": (ctypes.c_int, [u64, P, P, P, u32, u32, P, P]),
     }
@@ -131,6 +132,15 @@ def vocab_bytes(n: int, total_symbols: int, max_len: int) -> int:
     lib = load_library()
     out = ctypes.c_uint64()
     _check(lib.nw_vocab_bytes(n, total_symbols, max_len, ctypes.byref(out)))
+    return out.value
+
+
+def packed_issue_rate(blocks: int, trips: int, stream=None) -> int:
+    """Enqueue the packed-instruction issue-rate microbenchmark on `stream`;
+    returns the lane-instructions that launch issues (time it with events)."""
+    lib = load_library()
+    out = ctypes.c_uint64()
+    _check(lib.nw_packed_issue_rate(blocks, trips, ctypes.byref(out), _stream_handle(stream)))
     return out.value
 
 

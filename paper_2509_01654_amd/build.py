@@ -44,6 +44,7 @@ def _units():
         ("nw_batch", os.path.join(CSRC, "nw_batch.cpp"), []),
         ("nw_export", os.path.join(CSRC, "nw_export.cpp"), []),
         ("nw_graph", os.path.join(CSRC, "nw_graph.hip"), []),
+        ("k_peak", os.path.join(CSRC, "k_peak.hip"), []),
         ("k_launch", os.path.join(CSRC, "k_launch.hip"), []),
     ]
     for lo, hi in _la_splits():

@@ -108,3 +108,11 @@ def test_graph_and_export_arguments_rejected_on_the_host():
                                   None) == nw.NW_EINVAL
     f = nw._EdgeFilter(0, 0, 1, 1)
     assert lib.nw_all_pairs_edges(None, 0, 1, ctypes.byref(f), fake, fake, fake, 1, fake, None) == nw.NW_EINVAL
+
+
+def test_packed_rate_arguments_rejected_on_the_host():
+    lib = nw.load_library()
+    n = ctypes.c_uint64()
+    assert lib.nw_packed_issue_rate(0, 1, ctypes.byref(n), None) == nw.NW_EINVAL
+    assert lib.nw_packed_issue_rate(1, 0, ctypes.byref(n), None) == nw.NW_EINVAL
+    assert lib.nw_packed_issue_rate(1, 1, None, None) == nw.NW_EINVAL
