@@ -38,20 +38,28 @@ PEAK_ISSUE_CELLS = 256 * 64 * 2.4e9
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "topk_main_paper600k_counters.md")
 MAIN_PASS_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "nw_topk.h", "k_topk.h", "k_query.h",
                      "k_launch.hip", "k_inst.hip", "nw_api.cpp"]
+# the same for the 50,000-word int8 triangle (k_tri_tiled)
+TRI_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "tri_tiled_mid50k_counters.md")
+TRI_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "k_tri_tiled.h", "k_launch.hip", "k_inst.hip",
+               "nw_api.cpp"]
 
 
-def main_pass_sources_sha256() -> str:
+def sources_sha256(names) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in MAIN_PASS_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2509_01654_amd", "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
-def _summary_fields(prefix):
+def main_pass_sources_sha256() -> str:
+    return sources_sha256(MAIN_PASS_SOURCES)
+
+
+def _summary_fields(prefix, path=None):
     try:
-        text = open(COUNTER_SUMMARY, encoding="utf-8").read()
+        text = open(path or COUNTER_SUMMARY, encoding="utf-8").read()
     except OSError:
         return {}
     fields = {}
@@ -63,11 +71,12 @@ def _summary_fields(prefix):
     return fields
 
 
-def counter_traffic():
-    """(bytes fetched, bytes written) per main pass from the counter summary, or
-    None when there is none or the kernel sources changed since it was taken."""
-    fields = _summary_fields("traffic:")
-    if fields.get("sources_sha256") != main_pass_sources_sha256():
+def counter_traffic(path=None, sources=None):
+    """(bytes fetched, bytes written) per pass from a counter summary (the main
+    pass by default), or None when there is none or the kernel sources changed
+    since it was taken."""
+    fields = _summary_fields("traffic:", path)
+    if fields.get("sources_sha256") != sources_sha256(sources or MAIN_PASS_SOURCES):
         return None
     return float(fields["fetch_bytes"]), float(fields["write_bytes"])
 
@@ -503,10 +512,19 @@ def main():
         rec["config"] = {"workload": "all-pairs int8 triangle, 50,000 words (Zipf-40, clip(Poisson 7, 1, 20), "
                                      "+1/-1, gap -1)", "n_words": dv.n, "pairs": E, "cells": cells}
         achieved = OPS_PER_CELL * cells / (ms_per_step / 1e3)
+        tr = counter_traffic(TRI_COUNTER_SUMMARY, TRI_SOURCES)
         rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
-                           "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
+                           "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4),
+                           "traffic": None if tr is None else round(tr[0] + tr[1]),
                            "kernel": "k_tri_tiled (every LA)",
                            "issue_frac": round(cells / (ms_per_step / 1e3) / PEAK_ISSUE_CELLS, 4)}
+        if tr is not None:
+            # algorithmic bytes: one int8 score written per pair; the words read are ~1 MB
+            rec["roofline"]["traffic_detail"] = {
+                "unit": "HBM bytes per triangle (calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                "fetch": round(tr[0]), "write": round(tr[1]), "algorithmic_write": E,
+                "write_over_algorithmic": round(tr[1] / E, 4),
+                "GB_per_s": round((tr[0] + tr[1]) / (ms_per_step / 1e3) / 1e9, 1)}
         rec["output_GB_per_s"] = E / (ms_per_step / 1e3) / 1e9
     print(json.dumps(rec), flush=True)
 
