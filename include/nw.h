@@ -302,13 +302,18 @@ int64_t nw_clock_ns(void);
 
 /* ---------------------------------------------------------------------------
  * Batched form: the triangles of many dictionaries (each with its own words;
- * every dictionary symmetric) in one graph-captured sequence of persistent
- * launches.  Work items (dictionary, block pair, row length, chunk of row
- * pairs) are ordered heaviest first inside row-length classes; one persistent
- * kernel per class drains its queue.
+ * every dictionary symmetric) in one graph-captured sequence of launches.
+ * Persistent form: work items (dictionary, block pair, row length, chunk of
+ * row pairs) are ordered heaviest first inside row-length classes; one
+ * persistent kernel per class drains its queue.  Tiled form (class_width 0):
+ * every dictionary's per-length tiled launches, as nw_all_pairs_scores issues
+ * them, on forked library streams.  nw_batch_autotune times both.
  * ------------------------------------------------------------------------- */
 typedef struct {
-    uint32_t class_width;     /* 1: one persistent kernel per row length; 8: classes of 8 lengths */
+    uint32_t class_width;     /* 1: one persistent kernel per row length; 8: classes of 8 lengths;
+                                 0: no persistent kernels -- every dictionary's per-length tiled
+                                 launches, spread over library streams (wg_per_cu and
+                                 pairs_per_item unused) */
     uint32_t wg_per_cu;       /* persistent workgroups per compute unit (>= 1) */
     uint32_t pairs_per_item;  /* row pairs per work item (0 = all of a block and length) */
     uint32_t use_graph;       /* 1: capture once into a hipGraph and replay; 0: launch eagerly */

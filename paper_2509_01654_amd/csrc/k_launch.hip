@@ -6,7 +6,6 @@
 // row of the score matrix instead of the whole matrix).
 #define NW_LAUNCH_TU 1
 #include <algorithm>
-#include <mutex>
 
 #include "k_batch.h"
 #include "k_diag.h"
@@ -14,6 +13,7 @@
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_tri_tiled.h"
+#include "nw_fork.h"
 #include "nw_kernels.h"
 
 namespace nw {
@@ -87,93 +87,6 @@ const KernelTables &kernel_tables()
     return t;
 }
 
-// Independent launches (the per-length launches of one call, which write
-// disjoint outputs or commute through atomics) spread over the caller's
-// stream and kForkStreams library streams of the current device, so that the
-// tail of one launch overlaps the start of the next.  The library streams
-// first wait for the caller's work so far; the caller's stream then waits for
-// theirs, so the call stays ordered on the caller's stream.  The library
-// streams are created once per device and kept for the process; calls from
-// several host threads share them, which can serialize those calls against
-// each other but cannot deadlock: every wait binds to an event already
-// recorded, so each dependency points to work enqueued earlier.
-#ifndef NW_FORK_STREAMS
-#define NW_FORK_STREAMS 3
-#endif
-constexpr int kForkStreams = NW_FORK_STREAMS;
-
-class StreamFork {
-  public:
-    explicit StreamFork(hipStream_t caller) : caller_(caller) {}
-    StreamFork(const StreamFork &) = delete;
-    StreamFork &operator=(const StreamFork &) = delete;
-    ~StreamFork()
-    {
-        if (begun_ && !ended_) (void)end();   // an error path still joins what was launched
-        for (hipEvent_t &e : done_)
-            if (e) hipEventDestroy(e);
-        if (start_) hipEventDestroy(start_);
-    }
-    // every launch after begin() goes to next()
-    hipError_t begin()
-    {
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        if ((e = library_streams(dev, lib_)) != hipSuccess) return e;
-        if ((e = hipEventCreateWithFlags(&start_, hipEventDisableTiming)) != hipSuccess) return e;
-        if ((e = hipEventRecord(start_, caller_)) != hipSuccess) return e;
-        for (int i = 0; i < kForkStreams; ++i)
-            if ((e = hipStreamWaitEvent(lib_[i], start_, 0)) != hipSuccess) return e;
-        begun_ = true;
-        return hipSuccess;
-    }
-    hipStream_t next()
-    {
-        if (!begun_) return caller_;
-        const int i = turn_++ % (kForkStreams + 1);
-        used_[i] = true;
-        return i == 0 ? caller_ : lib_[i - 1];
-    }
-    // the caller's stream waits for every library stream that took a launch
-    hipError_t end()
-    {
-        ended_ = true;
-        for (int i = 0; i < kForkStreams; ++i) {
-            if (!used_[i + 1]) continue;
-            hipError_t e = hipEventCreateWithFlags(&done_[i], hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventRecord(done_[i], lib_[i]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(caller_, done_[i], 0);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    }
-
-  private:
-    static hipError_t library_streams(int dev, hipStream_t (&out)[kForkStreams])
-    {
-        static std::mutex mu;
-        static hipStream_t streams[64][kForkStreams] = {};
-        if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-        std::lock_guard<std::mutex> lock(mu);
-        for (int i = 0; i < kForkStreams; ++i) {
-            if (!streams[dev][i]) {
-                hipError_t e = hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking);
-                if (e != hipSuccess) return e;
-            }
-            out[i] = streams[dev][i];
-        }
-        return hipSuccess;
-    }
-    hipStream_t caller_;
-    hipStream_t lib_[kForkStreams] = {};
-    hipEvent_t start_ = nullptr;
-    hipEvent_t done_[kForkStreams] = {};
-    bool used_[kForkStreams + 1] = {};
-    bool begun_ = false, ended_ = false;
-    int turn_ = 0;
-};
-
 static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, hipStream_t stream, void **args)
 {
     if (lds > 65536) {
@@ -228,14 +141,17 @@ static uint32_t tile_chunks(uint64_t tiles, uint32_t maxrp)
 }
 
 hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
-                                 int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E)
+                                 int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E, StreamFork *shared)
 {
     if (idx_begin >= idx_end || V.n < 2) return hipSuccess;
     const TriGrid G = tri_grid(V, idx_begin, idx_end);
     const KernelTables &tab = kernel_tables();
-    StreamFork fork(stream);
-    hipError_t ef = fork.begin();
-    if (ef != hipSuccess) return ef;
+    StreamFork own(stream);
+    if (!shared) {
+        hipError_t ef = own.begin();
+        if (ef != hipSuccess) return ef;
+    }
+    StreamFork &fork = shared ? *shared : own;
     for (int LA = 0; LA <= V.lmax; ++LA) {
         if (h_maxrp[LA] == 0) continue;   // no block has row pairs of this length
         uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);
@@ -251,7 +167,7 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
                                   tri_lds_bytes(LA, V.alphabet, V.CB), fork.next(), args);
         if (e != hipSuccess) return e;
     }
-    return fork.end();
+    return shared ? hipSuccess : own.end();
 }
 
 hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,

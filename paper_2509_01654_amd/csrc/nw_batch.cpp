@@ -9,6 +9,10 @@
 // together.  The batch object captures [counter reset, one persistent kernel
 // per non-empty class] into a hipGraph once; each run replays it.
 //
+// Class width 0 is the other form: every dictionary's per-length tiled
+// launches (as nw_all_pairs_scores issues them), all spread over one fork of
+// library streams, captured into the same kind of graph.
+//
 // Autotuner: times candidate (class width, workgroups per CU, pairs per item)
 // settings on the batch itself and caches the best per device and workload
 // signature in a JSON-lines file.
@@ -23,6 +27,7 @@
 #include <vector>
 
 #include "k_batch.h"
+#include "nw_fork.h"
 #include "nw_host.h"
 #include "nw_kernels.h"
 
@@ -40,14 +45,19 @@ struct Plan {
     uint64_t off_vocabs = 0, off_outs = 0, off_counters = 0, off_items = 0;
 };
 
-int num_classes(int width) { return width == 1 ? kMaxLen + 1 : kNumClass8; }
+int num_classes(int width) { return width == 0 ? 0 : width == 1 ? kMaxLen + 1 : kNumClass8; }
 int class_of(int la, int width) { return width == 1 ? la : la / 8; }
 
 Plan make_plan(const nw_vocab *const *v, uint32_t nv, const nw_batch_options &o)
 {
     Plan P;
-    P.width = o.class_width == 1 ? 1 : 8;
+    P.width = o.class_width == 0 ? 0 : o.class_width == 1 ? 1 : 8;
     const int nc = num_classes(P.width);
+    if (P.width == 0) {   // tiled launches: no items, no counters
+        P.class_off.assign(1, 0);
+        P.ws_bytes = 256;
+        return P;
+    }
     std::vector<std::vector<std::pair<double, BatchItem>>> cls(nc);
     P.class_lds.assign(nc, 0);
     for (uint32_t vi = 0; vi < nv; ++vi) {
@@ -115,6 +125,7 @@ std::string device_name(int dev)
 
 struct nw_batch {
     std::vector<const nw_vocab *> v;
+    std::vector<void *> outs;   // host copies of d_outs
     nw_batch_options opt{};
     Plan plan;
     int out_kind = OUT_I16;
@@ -124,14 +135,30 @@ struct nw_batch {
     hipGraphExec_t exec = nullptr;
     int cus = 0;
 
-    // Enqueue the reset and the class kernels on stream s.
+    // Enqueue the reset and the class kernels on stream s.  The class
+    // kernels are independent (own counters, own items), so they are spread
+    // over library streams forked from s and joined back into it: in a
+    // captured graph they become parallel branches, and one class's tail
+    // overlaps the next class's start.
     hipError_t enqueue(hipStream_t s)
     {
+        if (plan.width == 0) {
+            StreamFork fork(s);
+            hipError_t e = fork.begin();
+            if (e != hipSuccess) return e;
+            for (size_t i = 0; i < v.size(); ++i)
+                if ((e = launch_triangle_tiled(v[i]->dev, v[i]->h_maxrp.data(), 0, v[i]->num_pairs, out_kind, outs[i],
+                                               s, nullptr, &fork)) != hipSuccess)
+                    return e;
+            return fork.end();
+        }
         const KernelTables &T = kernel_tables();
         const int nc = num_classes(plan.width);
         uint32_t *counters = reinterpret_cast<uint32_t *>(ws + plan.off_counters);
         hipError_t e = launch_reset_counters(counters, nc, s);
         if (e != hipSuccess) return e;
+        StreamFork fork(s);
+        if ((e = fork.begin()) != hipSuccess) return e;
         const DevVocab *vocabs = reinterpret_cast<const DevVocab *>(ws + plan.off_vocabs);
         const BatchItem *items = reinterpret_cast<const BatchItem *>(ws + plan.off_items);
         void *const *outs = reinterpret_cast<void *const *>(ws + plan.off_outs);
@@ -148,9 +175,9 @@ struct nw_batch {
             int kind = out_kind;
             uint32_t nn = n;
             void *args[] = {&vocabs, &it, &nn, &ctr, &outs, &kind};
-            if ((e = hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s)) != hipSuccess) return e;
+            if ((e = hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, fork.next())) != hipSuccess) return e;
         }
-        return hipSuccess;
+        return fork.end();
     }
 };
 
@@ -182,6 +209,7 @@ int nw_batch_create(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, 
     if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
     nw_batch *B = new nw_batch();
     B->v.assign(v, v + nv);
+    B->outs.assign(d_outs, d_outs + nv);
     B->opt = *opt;
     B->plan = make_plan(v, nv, *opt);
     B->out_kind = dt == NW_I8 ? OUT_I8 : OUT_I16;
@@ -193,15 +221,18 @@ int nw_batch_create(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, 
                     (unsigned long long)need);
     }
     hipError_t e = hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, v[0]->device);
-    // the plan's device image: dictionary descriptors, outputs, counters, items
-    std::vector<uint8_t> img(B->plan.ws_bytes, 0);
-    for (uint32_t i = 0; i < nv; ++i)
-        std::memcpy(img.data() + B->plan.off_vocabs + i * sizeof(DevVocab), &v[i]->dev, sizeof(DevVocab));
-    std::memcpy(img.data() + B->plan.off_outs, d_outs, 8ull * nv);
-    std::memcpy(img.data() + B->plan.off_items, B->plan.items.data(), sizeof(BatchItem) * B->plan.items.size());
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->ws, img.data(), img.size(), hipMemcpyHostToDevice, B->cap);
-    if (e == hipSuccess) e = hipStreamSynchronize(B->cap);
+    if (B->plan.width != 0) {
+        // the persistent plan's device image: dictionary descriptors, outputs,
+        // counters, items (the tiled form reads none of it)
+        std::vector<uint8_t> img(B->plan.ws_bytes, 0);
+        for (uint32_t i = 0; i < nv; ++i)
+            std::memcpy(img.data() + B->plan.off_vocabs + i * sizeof(DevVocab), &v[i]->dev, sizeof(DevVocab));
+        std::memcpy(img.data() + B->plan.off_outs, d_outs, 8ull * nv);
+        std::memcpy(img.data() + B->plan.off_items, B->plan.items.data(), sizeof(BatchItem) * B->plan.items.size());
+        if (e == hipSuccess) e = hipMemcpyAsync(B->ws, img.data(), img.size(), hipMemcpyHostToDevice, B->cap);
+        if (e == hipSuccess) e = hipStreamSynchronize(B->cap);
+    }
     if (e == hipSuccess && opt->use_graph) {
         e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
@@ -234,7 +265,13 @@ int nw_batch_info(const nw_batch *B, uint64_t *items, uint32_t *launches)
     if (items) *items = B->plan.items.size();
     if (launches) {
         uint32_t n = 0;
-        for (size_t c = 0; c + 1 < B->plan.class_off.size(); ++c) n += B->plan.class_off[c + 1] > B->plan.class_off[c];
+        if (B->plan.width == 0) {
+            for (const nw_vocab *x : B->v)
+                if (x->n >= 2)
+                    for (uint32_t c : x->h_maxrp) n += c > 0;
+        } else {
+            for (size_t c = 0; c + 1 < B->plan.class_off.size(); ++c) n += B->plan.class_off[c + 1] > B->plan.class_off[c];
+        }
         *launches = n;
     }
     return ok();
@@ -312,10 +349,11 @@ int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs
     nw_batch_options cur{8, 4, 64, 1};
     float cur_ms = 0;
     int rc = time_one(cur, cur_ms);
-    const uint32_t widths[] = {1, 8}, wgs[] = {2, 4, 8}, ppi[] = {16, 64, 0};
+    const uint32_t widths[] = {0, 1, 8}, wgs[] = {2, 4, 8}, ppi[] = {16, 64, 0};
     for (int dim = 0; dim < 3 && !rc; ++dim) {
+        if (dim > 0 && cur.class_width == 0) break;   // the tiled form has no persistent parameters
         const uint32_t *vals = dim == 0 ? widths : dim == 1 ? wgs : ppi;
-        const int nvals = dim == 0 ? 2 : 3;
+        const int nvals = 3;
         for (int t = 0; t < nvals && !rc; ++t) {
             nw_batch_options o = cur;
             (dim == 0 ? o.class_width : dim == 1 ? o.wg_per_cu : o.pairs_per_item) = vals[t];
