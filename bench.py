@@ -377,7 +377,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["paper", "mid", "batched", "diag", "edges", "export"], default="paper")
+    ap.add_argument("--workload", choices=["paper", "mid", "small", "batched", "diag", "edges", "export"],
+                    default="paper")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000",
@@ -516,10 +517,10 @@ def main():
             rec["cpu_baseline"] = cb
             rec["parity_sample"] = {"rows": rows, "bit_exact": ok}
     else:
-        rec["config"] = {"workload": "all-pairs int8 triangle, 50,000 words (Zipf-40, clip(Poisson 7, 1, 20), "
+        rec["config"] = {"workload": f"all-pairs int8 triangle, {dv.n:,} words (Zipf-40, clip(Poisson 7, 1, 20), "
                                      "+1/-1, gap -1)", "n_words": dv.n, "pairs": E, "cells": cells}
         achieved = OPS_PER_CELL * cells / (ms_per_step / 1e3)
-        tr = counter_traffic(TRI_COUNTER_SUMMARY, TRI_SOURCES)
+        tr = counter_traffic(TRI_COUNTER_SUMMARY, TRI_SOURCES) if args.workload == "mid" else None
         rec["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
                            "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4),
                            "traffic": None if tr is None else round(tr[0] + tr[1]),
