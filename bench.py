@@ -7,7 +7,7 @@ one step = the whole all-pairs pass producing every word's top-32 neighbours
 (int16 score, int32 index, ties by lower index) and the global score
 histogram: n(n-1)/2 = 1.8e11 pairs, every pair scored once.
 
-    python bench.py [--steps K] [--warmup W] [--workload paper|mid|batched|diag|edges|export] [--cpu-seconds S]
+    python bench.py [--steps K] [--warmup W] [--workload paper|mid|small|batched|diag|edges|export] [--cpu-seconds S]
 
 Prints one JSON line (see the design doc for every field).  --gpus N with N > 1
 exits: this build measures one GPU.
