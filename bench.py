@@ -9,8 +9,7 @@ histogram: n(n-1)/2 = 1.8e11 pairs, every pair scored once.
 
     python bench.py [--steps K] [--warmup W] [--workload paper|mid|small|batched|diag|edges|export] [--cpu-seconds S]
 
-Prints one JSON line (see the design doc for every field).  --gpus N with N > 1
-exits: this build measures one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -203,7 +202,9 @@ def bench_batched(args, nw, synth, torch, dev):
     dvs = [nw.Vocab(v.symbols, v.offsets, sc, device=dev) for v in vocabs]
     pairs = sum(d.num_pairs for d in dvs)
     cells = sum(d.num_cells for d in dvs)
-    cache = os.path.join(ROOT, "gpurun_out", "nw_autotune.jsonl") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    # the autotuner's cache of best settings per device and workload signature
+    import tempfile
+    cache = os.environ.get("NW_AUTOTUNE_CACHE") or os.path.join(tempfile.gettempdir(), "nw_autotune.jsonl")
     t0 = time.perf_counter()
     b = nw.Batch(dvs, torch.int16, autotune=True, cache_path=cache)
     tune_s = time.perf_counter() - t0
@@ -388,7 +389,7 @@ def main():
                     help="only run a plain 1 GiB device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
 
