@@ -25,14 +25,15 @@ struct BatchItem {
 
 // Dispatch a runtime row length to the tile instance of a class [L, HI].
 template <int L, int HI>
-__device__ __forceinline__ void tri_tile_dispatch(int la, const DevVocab &V, const BatchItem &I, void *out,
-                                                  int out_kind, uint8_t *lds)
+__device__ __forceinline__ void tri_tile_dispatch(int la, const DevVocab &V, uint32_t r, uint32_t b, uint32_t pbeg,
+                                                  uint32_t pend, uint64_t idx_begin, uint64_t idx_end, void *out,
+                                                  int out_kind, const EdgeSink &E, uint8_t *lds)
 {
     if constexpr (L <= HI) {
         if (la == L)
-            tri_tile<L>(V, I.r, I.b, I.pbeg, I.pend, 0, ~0ull, out, out_kind, EdgeSink{}, lds);
+            tri_tile<L>(V, r, b, pbeg, pend, idx_begin, idx_end, out, out_kind, E, lds);
         else
-            tri_tile_dispatch<L + 1, HI>(la, V, I, out, out_kind, lds);
+            tri_tile_dispatch<L + 1, HI>(la, V, r, b, pbeg, pend, idx_begin, idx_end, out, out_kind, E, lds);
     }
 }
 
@@ -51,8 +52,33 @@ __global__ __launch_bounds__(kThreads) void k_tri_persist(const DevVocab *vocabs
         if (it >= nitems) break;
         const BatchItem I = items[it];
         const DevVocab V = vocabs[I.vocab];
-        tri_tile_dispatch<LO, HI>(I.la, V, I, outs[I.vocab], out_kind, lds);
+        tri_tile_dispatch<LO, HI>(I.la, V, I.r, I.b, I.pbeg, I.pend, 0, ~0ull, outs[I.vocab], out_kind, EdgeSink{},
+                                  lds);
     }
+}
+
+// The triangle of a small dictionary with one launch per class of row
+// lengths [LO, HI] instead of one per length: workgroup (x, y) takes run
+// x % chunks (at most rpc row pairs) of tile x / chunks, and row length
+// LO + y.  Small dictionaries have little work per length, so the per-length
+// launches are bound by their host-side launch cost; this form issues a few
+// launches instead.
+template <int LO, int HI>
+__global__ __launch_bounds__(kThreads) void k_tri_class(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
+                                                        int out_kind, EdgeSink E, uint32_t rb0, uint32_t rbn,
+                                                        uint32_t chunks, uint32_t rpc)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t r, b;
+    if (!tile_block_pair(blockIdx.x / chunks, rb0, rbn, V.nb, r, b)) return;
+    const int la = LO + (int)blockIdx.y;
+    if (la > V.lmax) return;
+    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + la;
+    const uint64_t pbeg64 = (uint64_t)rpo[0] + (uint64_t)(blockIdx.x % chunks) * rpc;
+    if (pbeg64 >= rpo[1]) return;
+    const uint32_t pbeg = (uint32_t)pbeg64;
+    const uint32_t pend = rpo[1] - pbeg <= rpc ? rpo[1] : pbeg + rpc;
+    tri_tile_dispatch<LO, HI>(la, V, r, b, pbeg, pend, idx_begin, idx_end, out, out_kind, E, lds);
 }
 
 #ifdef NW_LAUNCH_TU

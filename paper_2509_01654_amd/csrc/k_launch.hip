@@ -130,6 +130,9 @@ static TriGrid tri_grid(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end)
 // tiles than workgroup slots (256 CUs x 6) splits its tiles into runs of at
 // least kMinRowPairs row pairs, up to about four workgroups per slot; short
 // runs cost more than they balance.
+// Dictionaries up to this many words take the class launches (k_tri_class).
+constexpr int64_t kClassLaunchMaxWords = 16384;
+
 static uint32_t tile_chunks(uint64_t tiles, uint32_t maxrp)
 {
     constexpr uint64_t kTargetWorkgroups = 256 * 6 * 4;
@@ -152,6 +155,37 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
         if (ef != hipSuccess) return ef;
     }
     StreamFork &fork = shared ? *shared : own;
+    if (V.n <= kClassLaunchMaxWords) {
+        // small dictionaries: one launch per class of 8 row lengths
+        // (k_tri_class; the per-length launches would be bound by launch cost)
+        for (int c = 0; c < kNumClass8 && 8 * c <= V.lmax; ++c) {
+            const int lo = 8 * c, hi = std::min(8 * c + 7, (int)V.lmax);
+            uint32_t rows = 0, maxrp = 0;
+            size_t lds = 0;
+            for (int LA = lo; LA <= hi; ++LA) {
+                rows += h_maxrp[LA];
+                maxrp = std::max(maxrp, h_maxrp[LA]);
+                lds = std::max<size_t>(lds, tri_lds_bytes(LA, V.alphabet, V.CB));
+            }
+            if (rows == 0) continue;
+            // runs of at least two row pairs, about 2048 workgroups per launch
+            const uint64_t ny = (uint64_t)(hi - lo + 1);
+            uint32_t chunks = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>((2048 + G.blocks * ny - 1) / (G.blocks * ny), (maxrp + 1) / 2));
+            uint32_t rpc = (maxrp + chunks - 1) / chunks;
+            DevVocab Vc = V;
+            uint64_t ib = idx_begin, ie = idx_end;
+            void *po = d_out;
+            int ok = out_kind;
+            EdgeSink es = E ? *E : EdgeSink{};
+            uint32_t rb0 = G.rb0, rbn = G.rbn;
+            void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
+            hipError_t e = launch_dyn(tab.class8[c], dim3((uint32_t)((uint64_t)G.blocks * chunks), (uint32_t)ny), lds,
+                                      fork.next(), args);
+            if (e != hipSuccess) return e;
+        }
+        return shared ? hipSuccess : own.end();
+    }
     for (int LA = 0; LA <= V.lmax; ++LA) {
         if (h_maxrp[LA] == 0) continue;   // no block has row pairs of this length
         uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);

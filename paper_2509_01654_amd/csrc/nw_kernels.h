@@ -20,6 +20,7 @@ struct KernelTables {
     const void *edges[kMaxLen + 1];      // threshold edge emitter
     const void *persist1[kMaxLen + 1];   // persistent batched kernel, one per row length
     const void *persist8[kNumClass8];    // persistent batched kernel, one per class of 8 lengths
+    const void *class8[kNumClass8];      // small-dictionary triangle kernel, one per class of 8 lengths
 };
 
 #define X(lo, hi) void nw_fill_##lo(KernelTables &t);
