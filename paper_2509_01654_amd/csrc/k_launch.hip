@@ -334,7 +334,7 @@ hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_of
         Q.partial = partial;
         void *args[] = {&Q};
         const dim3 grid((np + rpw - 1) / rpw, nsplit);
-        hipError_t e = launch_dyn(tab.query[LA], grid, query_lds_bytes(LA, V.alphabet), fork.next(), args);
+        hipError_t e = launch_dyn(tab.query[LA], grid, query_lds_bytes(LA, V.alphabet, k), fork.next(), args);
         if (e != hipSuccess) return e;
     }
     return fork_streams ? fork.end() : hipSuccess;
@@ -344,6 +344,11 @@ hipError_t launch_merge(const uint64_t *partial, int P, int kin, int64_t rows, i
                         int32_t *index, uint64_t *thr, int rank, hipStream_t stream)
 {
     if (rows <= 0) return hipSuccess;
+    if ((int64_t)P * kin >= 1024) {   // many keys per row: a workgroup each
+        hipLaunchKernelGGL(k_merge_lists_wg, dim3((uint32_t)rows), dim3(256), 0, stream, partial, P, kin, rows, kout, lo,
+                           score, index, thr, rank);
+        return hipGetLastError();
+    }
     const uint32_t grid = (uint32_t)((rows + 3) / 4);
     hipLaunchKernelGGL(k_merge_lists, dim3(grid), dim3(256), 0, stream, partial, P, kin, rows, kout, lo, score, index,
                        thr, rank);

@@ -10,11 +10,17 @@
 // words of a pair fill the two binary16 halves of the DP) and one split of the
 // column slots.  Per row pair it builds the LDS profile, then each wavefront
 // walks its share of the split (64 length-sorted column words per step) and
-// keeps a sorted wave list of the best k keys for each of the two rows.  Each
-// wave writes its two lists to `partial`, row-major [row][split*4 + wave][k].
+// keeps a sorted wave list of the best k keys for each of the two rows.  With
+// several splits the four wave lists of a row are merged in LDS (wavefront 0
+// for the first row, 1 for the second) into the split's list, written to
+// `partial`, row-major [row][split][k]; with one split (many rows, nothing to
+// spread) the four wave lists go out as they are, [row][wave][k].  Either
+// way a row has query_lists(nsplit) lists of k keys.
 //
 // k_merge_lists: one wavefront per row merges its P partial lists into the
-// final top-k (and optionally reports the key of a given rank).
+// final top-k (and optionally reports the key of a given rank);
+// k_merge_lists_wg does the same with a workgroup per row, for rows with many
+// partial keys (a few queries spread over many splits).
 #pragma once
 
 #include "nw_tile_common.h"
@@ -33,10 +39,14 @@ struct QueryArgs {
     int rpw;                // row pairs per workgroup
     int64_t per;            // column slots per split (multiple of 256)
     int nsplit;
-    uint64_t *partial;      // [rows][nsplit*4][k]
+    uint64_t *partial;      // [rows][nsplit][k]
 };
 
-__host__ __device__ constexpr uint32_t query_lds_bytes(int LA, int alphabet) { return 2u * profile_bytes(LA, alphabet); }
+// LDS: two profiles, then the wave lists of both rows of a pair (2 x 4 x k keys).
+__host__ __device__ constexpr uint32_t query_lds_bytes(int LA, int alphabet, int k)
+{
+    return 2u * profile_bytes(LA, alphabet) + 2u * 4u * 8u * (uint32_t)k;
+}
 
 template <int LA>
 __global__ __launch_bounds__(kThreads) void k_query_tiled(QueryArgs Q)
@@ -54,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void k_query_tiled(QueryArgs Q)
     const int wave = tid >> 6, lane = tid & 63;
     const uint32_t prof_bytes = profile_bytes(LA, Q.alphabet);
     const ProfileRole role = profile_role(tid, Q.alphabet);
-    const int P = Q.nsplit * 4;
+    uint64_t *wl = reinterpret_cast<uint64_t *>(lds + 2 * prof_bytes);   // [2 rows][4 waves][k]
 
     for (uint32_t p = pbeg; p < pend; ++p) {
         const int32_t a0 = Q.R.pairs[2 * p], a1 = Q.R.pairs[2 * p + 1];
@@ -76,14 +86,30 @@ __global__ __launch_bounds__(kThreads) void k_query_tiled(QueryArgs Q)
             wl_offer(list0, thr0, key0, Q.k, lane);
             if (a1 >= 0) wl_offer(list1, thr1, key1, Q.k, lane);
         }
-        if (lane < Q.k) {
-            const int32_t r0 = Q.R.orig[a0];
-            Q.partial[((int64_t)r0 * P + split * 4 + wave) * Q.k + lane] = list0;
-            if (a1 >= 0) {
-                const int32_t r1 = Q.R.orig[a1];
-                Q.partial[((int64_t)r1 * P + split * 4 + wave) * Q.k + lane] = list1;
+        if (Q.nsplit == 1) {   // uniform: the wave lists are the row's partial lists
+            if (lane < Q.k) {
+                Q.partial[((int64_t)Q.R.orig[a0] * 4 + wave) * Q.k + lane] = list0;
+                if (a1 >= 0) Q.partial[((int64_t)Q.R.orig[a1] * 4 + wave) * Q.k + lane] = list1;
             }
+            continue;
         }
+        if (lane < Q.k) {
+            wl[(0 * 4 + wave) * Q.k + lane] = list0;
+            wl[(1 * 4 + wave) * Q.k + lane] = list1;
+        }
+        __syncthreads();
+        // wavefront h merges the four wave lists of row h of the pair
+        if (wave < 2 && (wave == 0 || a1 >= 0)) {
+            const uint64_t *src = wl + wave * 4 * Q.k;
+            uint64_t list = 0, t = 0;
+            for (int base = 0; base < 4 * Q.k; base += 64) {
+                const int i = base + lane;
+                wl_offer(list, t, i < 4 * Q.k ? src[i] : 0, Q.k, lane);
+            }
+            const int32_t row = Q.R.orig[wave == 0 ? a0 : a1];
+            if (lane < Q.k) Q.partial[((int64_t)row * Q.nsplit + split) * Q.k + lane] = list;
+        }
+        __syncthreads();   // the wave lists are rewritten by the next row pair
     }
 }
 
@@ -111,6 +137,42 @@ __global__ __launch_bounds__(256) void k_merge_lists(const uint64_t *partial, in
     }
     if (thr != nullptr) {
         const uint64_t v = readlane64(list, rank - 1);
+        if (lane == 0) thr[row] = v;
+    }
+}
+
+// The same with one workgroup per row: wavefront w merges the w-th quarter of
+// the row's P * kin keys, then wavefront 0 merges the four lists (LDS).
+__global__ __launch_bounds__(256) void k_merge_lists_wg(const uint64_t *partial, int P, int kin, int64_t rows, int kout,
+                                                        int lo, int16_t *score, int32_t *index, uint64_t *thr, int rank)
+{
+    __shared__ uint64_t quarter[4 * 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row = blockIdx.x;
+    if (row >= rows) return;   // uniform over the workgroup
+    const uint64_t *src = partial + row * (int64_t)P * kin;
+    const int total = P * kin;
+    const int per = (total + 3) / 4;
+    const int b0 = min(total, wave * per), b1 = min(total, b0 + per);
+    uint64_t list = 0, t = 0;
+    for (int base = b0; base < b1; base += 64) {
+        const int i = base + lane;
+        wl_offer(list, t, i < b1 ? src[i] : 0, kout, lane);
+    }
+    if (lane < kout) quarter[wave * kout + lane] = list;
+    __syncthreads();
+    if (wave != 0) return;
+    uint64_t fin = 0, tf = 0;
+    for (int base = 0; base < 4 * kout; base += 64) {
+        const int i = base + lane;
+        wl_offer(fin, tf, i < 4 * kout ? quarter[i] : 0, kout, lane);
+    }
+    if (score != nullptr && lane < kout) {
+        score[row * kout + lane] = fin ? (int16_t)key_score(fin, lo) : (int16_t)-32768;
+        index[row * kout + lane] = fin ? key_index(fin) : -1;
+    }
+    if (thr != nullptr) {
+        const uint64_t v = readlane64(fin, rank - 1);
         if (lane == 0) thr[row] = v;
     }
 }

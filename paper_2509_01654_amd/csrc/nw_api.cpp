@@ -175,7 +175,7 @@ TopkWs topk_ws(uint64_t n, uint32_t k)
     w.thr = take(8 * n);
     w.cnt = take(4 * n);
     w.ovf = take(4 + 4 * n);
-    w.partial = take(8 * n * 4 * (uint64_t)(k + 1));
+    w.partial = take(8 * n * (uint64_t)query_lists(1) * (k + 1));
     w.lists = take(8 * n * (uint64_t)w.cap);
     w.total = o;
     return w;
@@ -188,7 +188,7 @@ int query_splits(uint64_t n_q)
     // enough workgroups to fill the GPU when few queries are in flight
     const uint64_t pairs = (n_q + 1) / 2;
     uint64_t s = pairs ? (2048 + pairs - 1) / pairs : 1;
-    return (int)std::min<uint64_t>(64, std::max<uint64_t>(1, s));
+    return (int)std::min<uint64_t>(256, std::max<uint64_t>(1, s));
 }
 
 QueryWs query_ws(uint64_t n_q, uint32_t k)
@@ -205,7 +205,7 @@ QueryWs query_ws(uint64_t n_q, uint32_t k)
     w.pairs = take((n_q + kMaxLen + 1) * 8);
     w.off = take((kMaxLen + 2) * 4);
     w.orig = take(n_q * 4);
-    w.partial = take(n_q * (uint64_t)w.nsplit * 4 * k * 8);
+    w.partial = take(n_q * (uint64_t)query_lists(w.nsplit) * k * 8);
     w.total = o;
     return w;
 }
@@ -711,7 +711,7 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     P.nslots = D.pslots;
     if ((e = launch_query(D, R, v->h_gp_off.data(), P, (int)k + 1, 1, partial, st, true)) != hipSuccess)
         return dev_fail(e, "launching the threshold pre-pass");
-    if ((e = launch_merge(partial, 4, (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
+    if ((e = launch_merge(partial, query_lists(1), (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
         return dev_fail(e, "launching the threshold merge");
     if ((e = hipEventRecord(vm->ev[1], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 2. every unordered pair once: candidates for both endpoints, histogram.
@@ -759,7 +759,7 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     const int nsplit = 16;
     const uint64_t area = 8 * n * (uint64_t)W.cap;
     const uint64_t fixed = align_up((kMaxLen + 2) * 4, 256) + 8 * 256;
-    const uint64_t per_word = kWordBytes + 8 + 4 + 4 + (uint64_t)nsplit * 4 * kq * 8 + (uint64_t)kq * 6;
+    const uint64_t per_word = kWordBytes + 8 + 4 + 4 + (uint64_t)query_lists(nsplit) * kq * 8 + (uint64_t)kq * 6;
     const uint64_t batch = area > fixed ? (area - fixed) / per_word : 0;
     if (batch == 0) return fail(NW_ENOMEM, "the candidate lists are too small to recompute an overflowed word");
     for (uint64_t t0 = 0; t0 < novf; t0 += batch) {
@@ -776,7 +776,7 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
         uint32_t *qoff = reinterpret_cast<uint32_t *>(q); q += align_up((kMaxLen + 2) * 4, 256);
         int32_t *qorig = reinterpret_cast<int32_t *>(q); q += align_up(img.orig.size() * 4, 256);
         int32_t *qwords = reinterpret_cast<int32_t *>(q); q += align_up(4ull * B, 256);
-        uint64_t *qpart = reinterpret_cast<uint64_t *>(q); q += align_up((uint64_t)B * nsplit * 4 * kq * 8, 256);
+        uint64_t *qpart = reinterpret_cast<uint64_t *>(q); q += align_up((uint64_t)B * query_lists(nsplit) * kq * 8, 256);
         int32_t *qi = reinterpret_cast<int32_t *>(q); q += align_up((uint64_t)B * kq * 4, 256);
         int16_t *qs = reinterpret_cast<int16_t *>(q);
         if ((e = hipMemcpy(qsym, img.sym.data(), img.sym.size(), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -791,7 +791,7 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
         QR.off = qoff;
         QR.orig = qorig;
         if ((e = launch_query(D, QR, img.off.data(), full_colset(D), kq, nsplit, qpart, st)) != hipSuccess ||
-            (e = launch_merge(qpart, nsplit * 4, kq, B, kq, D.lo, qs, qi, nullptr, 1, st)) != hipSuccess ||
+            (e = launch_merge(qpart, query_lists(nsplit), kq, B, kq, D.lo, qs, qi, nullptr, 1, st)) != hipSuccess ||
             (e = launch_scatter_lists(qs, qi, qwords, B, kq, (int)k, d_score, d_index, st)) != hipSuccess)
             return dev_fail(e, "launching the overflow recomputation");
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail(e, "recomputing overflowed words");
@@ -886,7 +886,7 @@ int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_
     Dq.lo = (int32_t)lo;
     uint64_t *partial = reinterpret_cast<uint64_t *>(ws + W.partial);
     if ((e = launch_query(Dq, R, img.off.data(), full_colset(D), (int)k, W.nsplit, partial, st)) != hipSuccess ||
-        (e = launch_merge(partial, W.nsplit * 4, (int)k, (int64_t)n_q, (int)k, (int)lo, d_score, d_index, nullptr, 1, st)) != hipSuccess)
+        (e = launch_merge(partial, query_lists(W.nsplit), (int)k, (int64_t)n_q, (int)k, (int)lo, d_score, d_index, nullptr, 1, st)) != hipSuccess)
         return dev_fail(e, "launching the query kernels");
     return ok();
 }

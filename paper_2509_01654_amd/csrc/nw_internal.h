@@ -126,9 +126,13 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
                                 uint64_t idx_begin, uint64_t idx_end, int out_kind, void *d_out, hipStream_t stream,
                                 const EdgeSink *E = nullptr);
 
+// Partial lists per row of a query launch over nsplit column splits: the four
+// wavefront lists with one split, one merged list per split otherwise.
+__host__ __device__ constexpr int query_lists(int nsplit) { return nsplit == 1 ? 4 : nsplit; }
+
 // Per-row top-k lists of the rows R (pairs grouped by length, h_off = host
 // copy of R.off) against the column set C, split over nsplit column ranges:
-// partial[row][nsplit*4][k].  Scoring from V.  fork_streams spreads the
+// partial[row][query_lists(nsplit)][k].  Scoring from V.  fork_streams spreads the
 // per-length launches over library streams (throughput calls; latency-bound
 // callers such as the server keep them on `stream`).
 hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_off, const ColSet &C, int k,

@@ -135,7 +135,7 @@ struct nw_server {
         Dq.lo = (int32_t)lo;
         uint64_t *partial = reinterpret_cast<uint64_t *>(s.d_ws + W.partial);
         if ((e = launch_query(Dq, R, img.off.data(), full_colset(v->dev), (int)k, W.nsplit, partial, s.st)) != hipSuccess ||
-            (e = launch_merge(partial, W.nsplit * 4, (int)k, q, (int)k, (int)lo, s.d_s, s.d_i, nullptr, 1, s.st)) !=
+            (e = launch_merge(partial, query_lists(W.nsplit), (int)k, q, (int)k, (int)lo, s.d_s, s.d_i, nullptr, 1, s.st)) !=
                 hipSuccess ||
             (e = hipMemcpyAsync(s.h_s, s.d_s, (size_t)q * k * 2, hipMemcpyDeviceToHost, s.st)) != hipSuccess ||
             (e = hipMemcpyAsync(s.h_i, s.d_i, (size_t)q * k * 4, hipMemcpyDeviceToHost, s.st)) != hipSuccess ||
