@@ -248,7 +248,8 @@ def bench_batched(args, nw, synth, torch, dev):
                    "autotune_s": round(tune_s, 1)},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(PEAK_16BIT_OPS / 1e12, 2),
                      "unit": "Tops/s (16-bit)", "frac": round(achieved / PEAK_16BIT_OPS, 4), "traffic": None,
-                     "kernel": ("k_tri_tiled (graph replay of every dictionary's per-length launches)"
+                     "kernel": ("k_tri_tiled / k_tri_class (every dictionary's launches"
+                                + (", graph replay)" if b.options["use_graph"] else ", eager on forked streams)")
                                 if b.options["class_width"] == 0 else "k_tri_persist (graph replay)"),
                      "issue_frac": round(cells / (ms / 1e3) / PEAK_ISSUE_CELLS, 4)},
         "output_GB_per_s": round(2 * pairs / (ms / 1e3) / 1e9, 1),

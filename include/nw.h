@@ -316,7 +316,9 @@ typedef struct {
                                  pairs_per_item unused) */
     uint32_t wg_per_cu;       /* persistent workgroups per compute unit (>= 1) */
     uint32_t pairs_per_item;  /* row pairs per work item (0 = all of a block and length) */
-    uint32_t use_graph;       /* 1: capture once into a hipGraph and replay; 0: launch eagerly */
+    uint32_t use_graph;       /* 1: capture once into a hipGraph and replay; 0: launch eagerly.
+                                 Launches that are spread over library streams when
+                                 eager stay on one stream inside a capture. */
 } nw_batch_options;
 
 typedef struct nw_batch nw_batch;
@@ -341,7 +343,8 @@ int nw_batch_info(const nw_batch *b, uint64_t *items, uint32_t *launches);
 void nw_batch_destroy(nw_batch *b);
 
 /* Choose nw_batch_options for this batch by timing candidates on it
- * (coordinate search over class width, workgroups per CU and pairs per item;
+ * (the tiled form launched eagerly, then a coordinate search over class
+ * width, workgroups per CU and pairs per item with graphs;
  * the workspace must hold the largest candidate plan, see
  * nw_batch_workspace_bytes with pairs_per_item = 16).  With cache_path, a
  * result cached for the same device and workload signature is returned

@@ -487,7 +487,8 @@ class Batch:
             _check(lib.nw_batch_autotune(self._vh, nv, self._oh, self.dt, ctypes.c_void_p(self.ws.data_ptr()),
                                          self.ws.numel(), _stream_handle(stream), cp, ctypes.byref(opt),
                                          ctypes.byref(ms)))
-            opt.use_graph = 1 if use_graph else 0
+            if not use_graph:   # the caller forbids graphs; otherwise keep the tuner's choice
+                opt.use_graph = 0
             self.tuned_ms = ms.value
         self.options = dict(class_width=opt.class_width, wg_per_cu=opt.wg_per_cu,
                             pairs_per_item=opt.pairs_per_item, use_graph=opt.use_graph)

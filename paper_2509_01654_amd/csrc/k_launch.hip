@@ -130,9 +130,6 @@ static TriGrid tri_grid(const DevVocab &V, uint64_t idx_begin, uint64_t idx_end)
 // tiles than workgroup slots (256 CUs x 6) splits its tiles into runs of at
 // least kMinRowPairs row pairs, up to about four workgroups per slot; short
 // runs cost more than they balance.
-// Dictionaries up to this many words take the class launches (k_tri_class).
-constexpr int64_t kClassLaunchMaxWords = 16384;
-
 static uint32_t tile_chunks(uint64_t tiles, uint32_t maxrp)
 {
     constexpr uint64_t kTargetWorkgroups = 256 * 6 * 4;

@@ -265,10 +265,19 @@ int nw_batch_info(const nw_batch *B, uint64_t *items, uint32_t *launches)
     if (items) *items = B->plan.items.size();
     if (launches) {
         uint32_t n = 0;
-        if (B->plan.width == 0) {
-            for (const nw_vocab *x : B->v)
-                if (x->n >= 2)
+        if (B->plan.width == 0) {   // as launch_triangle_tiled issues them
+            for (const nw_vocab *x : B->v) {
+                if (x->n < 2) continue;
+                if ((int64_t)x->n <= kClassLaunchMaxWords) {
+                    for (size_t c = 0; c < x->h_maxrp.size(); c += 8) {
+                        uint32_t rows = 0;
+                        for (size_t la = c; la < std::min(c + 8, x->h_maxrp.size()); ++la) rows += x->h_maxrp[la];
+                        n += rows > 0;
+                    }
+                } else {
                     for (uint32_t c : x->h_maxrp) n += c > 0;
+                }
+            }
         } else {
             for (size_t c = 0; c + 1 < B->plan.class_off.size(); ++c) n += B->plan.class_off[c + 1] > B->plan.class_off[c];
         }
@@ -310,10 +319,12 @@ int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs
             if (line.find("\"key\": \"" + k + "\"") == std::string::npos) continue;
             nw_batch_options o{};
             float ms = 0;
-            if (std::sscanf(line.c_str() + line.find("\"class_width\""),
-                            "\"class_width\": %u, \"wg_per_cu\": %u, \"pairs_per_item\": %u, \"ms\": %f",
-                            &o.class_width, &o.wg_per_cu, &o.pairs_per_item, &ms) == 4) {
-                o.use_graph = 1;
+            const size_t at = line.find("\"class_width\"");
+            if (at == std::string::npos) continue;
+            if (std::sscanf(line.c_str() + at,
+                            "\"class_width\": %u, \"wg_per_cu\": %u, \"pairs_per_item\": %u, \"use_graph\": %u, "
+                            "\"ms\": %f",
+                            &o.class_width, &o.wg_per_cu, &o.pairs_per_item, &o.use_graph, &ms) == 5) {
                 *best = o;
                 if (best_ms) *best_ms = ms;
                 return ok();
@@ -350,6 +361,17 @@ int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs
     float cur_ms = 0;
     int rc = time_one(cur, cur_ms);
     const uint32_t widths[] = {0, 1, 8}, wgs[] = {2, 4, 8}, ppi[] = {16, 64, 0};
+    // the tiled form launched eagerly (its launches overlap on forked streams,
+    // which a captured graph does not do)
+    if (!rc) {
+        const nw_batch_options o{0, 1, 0, 0};
+        float ms = 0;
+        rc = time_one(o, ms);
+        if (!rc && ms < cur_ms) {
+            cur = o;
+            cur_ms = ms;
+        }
+    }
     for (int dim = 0; dim < 3 && !rc; ++dim) {
         if (dim > 0 && cur.class_width == 0) break;   // the tiled form has no persistent parameters
         const uint32_t *vals = dim == 0 ? widths : dim == 1 ? wgs : ppi;
@@ -378,7 +400,8 @@ int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs
     if (cache_path) {
         std::ofstream out(cache_path, std::ios::app);
         out << "{\"key\": \"" << k << "\", \"class_width\": " << cur.class_width << ", \"wg_per_cu\": " << cur.wg_per_cu
-            << ", \"pairs_per_item\": " << cur.pairs_per_item << ", \"ms\": " << cur_ms << "}\n";
+            << ", \"pairs_per_item\": " << cur.pairs_per_item << ", \"use_graph\": " << cur.use_graph
+            << ", \"ms\": " << cur_ms << "}\n";
     }
     return ok();
 }

@@ -34,11 +34,17 @@ class StreamFork {
             if (e) hipEventDestroy(e);
         if (start_) hipEventDestroy(start_);
     }
-    // every launch after begin() goes to next()
+    // every launch after begin() goes to next().  A caller's stream that is
+    // being captured into a graph is not forked: the launches stay on it, in
+    // order (no library streams or events enter a capture).
     hipError_t begin()
     {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(caller_, &cs);
+        if (e != hipSuccess) return e;
+        if (cs != hipStreamCaptureStatusNone) return hipSuccess;
         int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
+        e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
         if ((e = library_streams(dev, lib_)) != hipSuccess) return e;
         if ((e = hipEventCreateWithFlags(&start_, hipEventDisableTiming)) != hipSuccess) return e;

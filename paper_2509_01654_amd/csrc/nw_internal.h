@@ -104,8 +104,11 @@ struct EdgeSink {
 // OUT_EDGES the pairs of that range go to the edge sink E instead of d_out.
 // h_maxrp[LA] (host) = most row pairs of length LA in one block: sets how
 // far tiles are split when the launch has few of them.
-// With `shared`, the launches join that fork (begun and ended by the caller)
+// Dictionaries of at most kClassLaunchMaxWords words take one launch per class
+// of 8 row lengths (k_tri_class), larger ones one launch per row length.  With
+// `shared`, the launches join that fork (begun and ended by the caller)
 // instead of one of their own.
+constexpr int64_t kClassLaunchMaxWords = 16384;
 class StreamFork;
 hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
                                  int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E = nullptr,
