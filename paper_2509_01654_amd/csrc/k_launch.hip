@@ -87,6 +87,16 @@ const KernelTables &kernel_tables()
     return t;
 }
 
+// A launch through a fork (a stream, or a node of a graph).
+static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, StreamFork &fork, void **args)
+{
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return fork.launch(fn, grid, dim3(kThreads), lds, args);
+}
+
 static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, hipStream_t stream, void **args)
 {
     if (lds > 65536) {
@@ -178,7 +188,7 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
             uint32_t rb0 = G.rb0, rbn = G.rbn;
             void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
             hipError_t e = launch_dyn(tab.class8[c], dim3((uint32_t)((uint64_t)G.blocks * chunks), (uint32_t)ny), lds,
-                                      fork.next(), args);
+                                      fork, args);
             if (e != hipSuccess) return e;
         }
         return shared ? hipSuccess : own.end();
@@ -195,7 +205,7 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
         uint32_t rb0 = G.rb0, rbn = G.rbn;
         void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &chunks, &rpc};
         hipError_t e = launch_dyn(tab.tri[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
-                                  tri_lds_bytes(LA, V.alphabet, V.CB), fork.next(), args);
+                                  tri_lds_bytes(LA, V.alphabet, V.CB), fork, args);
         if (e != hipSuccess) return e;
     }
     return shared ? hipSuccess : own.end();

@@ -9,9 +9,9 @@
 // together.  The batch object captures [counter reset, one persistent kernel
 // per non-empty class] into a hipGraph once; each run replays it.
 //
-// Class width 0 is the other form: every dictionary's per-length tiled
-// launches (as nw_all_pairs_scores issues them), all spread over one fork of
-// library streams, captured into the same kind of graph.
+// Class width 0 is the other form: every dictionary's launches (as
+// nw_all_pairs_scores issues them), spread over one fork of library streams
+// when eager, or built into a graph as kernel nodes without dependencies.
 //
 // Autotuner: times candidate (class width, workgroups per CU, pairs per item)
 // settings on the batch itself and caches the best per device and workload
@@ -234,11 +234,23 @@ int nw_batch_create(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, 
         if (e == hipSuccess) e = hipStreamSynchronize(B->cap);
     }
     if (e == hipSuccess && opt->use_graph) {
-        e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t e2 = B->enqueue(B->cap);
-            e = hipStreamEndCapture(B->cap, &B->graph);
-            if (e2 != hipSuccess) e = e2;
+        if (B->plan.width == 0) {
+            // the tiled form's graph is built node by node: every launch is a
+            // kernel node with no dependencies, so they overlap on replay
+            e = hipGraphCreate(&B->graph, 0);
+            if (e == hipSuccess) {
+                StreamFork nodes(B->graph);
+                for (size_t i = 0; i < B->v.size() && e == hipSuccess; ++i)
+                    e = launch_triangle_tiled(B->v[i]->dev, B->v[i]->h_maxrp.data(), 0, B->v[i]->num_pairs,
+                                              B->out_kind, B->outs[i], nullptr, nullptr, &nodes);
+            }
+        } else {
+            e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = B->enqueue(B->cap);
+                e = hipStreamEndCapture(B->cap, &B->graph);
+                if (e2 != hipSuccess) e = e2;
+            }
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
     }

@@ -25,6 +25,10 @@ constexpr int kForkStreams = NW_FORK_STREAMS;
 class StreamFork {
   public:
     explicit StreamFork(hipStream_t caller) : caller_(caller) {}
+    // Graph mode: every launch becomes a kernel node of `graph` without
+    // dependencies, so the nodes of one graph may run side by side on replay
+    // (no streams or events are involved; begin and end do nothing).
+    explicit StreamFork(hipGraph_t graph) : caller_(nullptr), graph_(graph) {}
     StreamFork(const StreamFork &) = delete;
     StreamFork &operator=(const StreamFork &) = delete;
     ~StreamFork()
@@ -39,6 +43,7 @@ class StreamFork {
     // order (no library streams or events enter a capture).
     hipError_t begin()
     {
+        if (graph_) return hipSuccess;
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         hipError_t e = hipStreamIsCapturing(caller_, &cs);
         if (e != hipSuccess) return e;
@@ -60,6 +65,22 @@ class StreamFork {
         const int i = turn_++ % (kForkStreams + 1);
         used_[i] = true;
         return i == 0 ? caller_ : lib_[i - 1];
+    }
+    // One launch: on next()'s stream, or as a node of the graph.
+    hipError_t launch(const void *fn, dim3 grid, dim3 block, size_t lds, void **args)
+    {
+        if (graph_) {
+            hipKernelNodeParams p{};
+            p.func = const_cast<void *>(fn);
+            p.gridDim = grid;
+            p.blockDim = block;
+            p.sharedMemBytes = (unsigned int)lds;
+            p.kernelParams = args;   // the values are copied into the node
+            p.extra = nullptr;
+            hipGraphNode_t node;
+            return hipGraphAddKernelNode(&node, graph_, nullptr, 0, &p);
+        }
+        return hipLaunchKernel(fn, grid, block, args, lds, next());
     }
     // the caller's stream waits for every library stream that took a launch
     hipError_t end()
@@ -92,6 +113,7 @@ class StreamFork {
         return hipSuccess;
     }
     hipStream_t caller_;
+    hipGraph_t graph_ = nullptr;
     hipStream_t lib_[kForkStreams] = {};
     hipEvent_t start_ = nullptr;
     hipEvent_t done_[kForkStreams] = {};
