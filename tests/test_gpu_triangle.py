@@ -58,6 +58,17 @@ def test_ragged_sizes(n):
     np.testing.assert_array_equal(got, _oracle_triangle(v, PM1))
 
 
+@pytest.mark.parametrize("n", [16384, 16385])
+def test_launch_form_switch(n):
+    """Both sides of the switch between one launch per class of 8 row lengths
+    (at most 16,384 words, 256-word blocks) and one launch per length (larger
+    dictionaries, 1,024-word blocks): the whole triangle against the oracle."""
+    _report(f"launch-form switch n={n}")
+    v = synth.zipf_vocab(n, seed=2000 + n, mean_len=7.0, max_len=20)
+    _, got = _gpu_triangle(v, PM1, torch.int8)
+    np.testing.assert_array_equal(got, _oracle_triangle(v, PM1))
+
+
 def test_empty_and_single_word():
     nw = _nw()
     for n in (0, 1):
