@@ -9,15 +9,17 @@
  * (Plein, "Parallel Needleman-Wunsch on CUDA to measure word similarity based
  * on phonetic transcriptions", 2025):
  *
- *   - orc_score: Algorithm 1 ("Needleman-Wunsch", Section 2) step by step, with
- *     the full (len(A)+1) x (len(B)+1) score matrix held in int32.
+ *   - orc_score: the global-alignment score of Section 2 from its prefix
+ *     recurrence (the table Algorithm 1 fills), one int32 row at a time;
+ *     orc_matrix returns the whole table for the worked examples.
  *   - orc_triangle: the upper triangle of the adjacency matrix traversed in
  *     row-major order (0,1),(0,2),...,(n-2,n-1) (Section 4.1), with
  *     A = word i (row) and B = word j (column).
  *   - orc_topk_rows / orc_query: for each word, score it against every other
- *     word (every dictionary word for a query), sort all results by
- *     (score descending, index ascending) and keep the first k.  Not in the
- *     paper; this is the plain definition of a per-word neighbour list.
+ *     word (every dictionary word for a query) and keep the k first under the
+ *     order (score descending, index ascending), offered one by one to a
+ *     sorted list of at most k entries.  Not in the paper; this is the plain
+ *     definition of a per-word neighbour list.
  *   - histogram: a count of unordered pairs (i < j) per integer score.
  *
  * Threads (POSIX) only split rows, like the paper's Rayon loop over the outer
@@ -29,53 +31,77 @@
 #include <string.h>
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm 1 (Section 2).                                                  */
-/*   sim[x * alphabet + y] is similarity(x, y) for symbol x of A, y of B.    */
-/*   gap is the linear gap penalty p, added once per gap symbol.             */
-/*   M must hold (la+1)*(lb+1) int32; cell (i,j) lives at i*(lb+1)+j, which  */
-/*   is the paper's row-major layout of the score matrix.                    */
+/* The score of one pair (Section 2).                                        */
+/*                                                                           */
+/* V(i, j) is the best score of a global alignment of the first i symbols   */
+/* of A with the first j symbols of B.  The last column of such an          */
+/* alignment pairs A_i with B_j, or sets A_i against a gap, or B_j against  */
+/* a gap, so                                                                 */
+/*   V(i, 0) = i p,   V(0, j) = j p,                                         */
+/*   V(i, j) = max(V(i-1, j-1) + sim(A_i, B_j), V(i-1, j) + p, V(i, j-1) + p) */
+/* and score(A, B) = V(len A, len B): the table Algorithm 1 fills.           */
+/*   sim[x * alphabet + y] is the similarity of symbol x of A and y of B;    */
+/*   gap is the linear penalty p, added once per gap symbol.                 */
+/*                                                                           */
+/* Only one row of V is kept: `line` (lb+1 int32) holds V(i-1, .) before     */
+/* row i is computed over it, left to right.  When `table` is non-NULL,      */
+/* every finished row i is also copied to table[i*(lb+1) ..], which gives    */
+/* the whole (la+1) x (lb+1) table in row-major order.                       */
 /* ------------------------------------------------------------------------ */
-int32_t orc_score(const uint8_t *A, int64_t la, const uint8_t *B, int64_t lb,
-                  const int32_t *sim, int32_t alphabet, int32_t gap, int32_t *M)
+static int32_t prefix_scores(const uint8_t *A, int64_t la, const uint8_t *B, int64_t lb,
+                             const int32_t *sim, int32_t alphabet, int32_t gap,
+                             int32_t *line, int32_t *table)
 {
-    const int64_t W = lb + 1;
-    /* first column: scoreMatrix[i][0] = p * i */
-    for (int64_t i = 0; i <= la; ++i) M[i * W + 0] = gap * (int32_t)i;
-    /* first row: scoreMatrix[0][j] = p * j */
-    for (int64_t j = 0; j <= lb; ++j) M[0 * W + j] = gap * (int32_t)j;
-    /* nested loops, row-wise, indices from 1 */
+    const size_t row_bytes = sizeof(int32_t) * (size_t)(lb + 1);
+    for (int64_t j = 0; j <= lb; ++j) line[j] = (int32_t)j * gap;
+    if (table) memcpy(table, line, row_bytes);
     for (int64_t i = 1; i <= la; ++i) {
+        int32_t corner = line[0];              /* V(i-1, j-1) for j = 1 */
+        int32_t left = (int32_t)i * gap;       /* V(i, j-1) for j = 1 */
+        line[0] = left;
         for (int64_t j = 1; j <= lb; ++j) {
-            int32_t cost = sim[(int64_t)A[i - 1] * alphabet + B[j - 1]];
-            int32_t matchScore = M[(i - 1) * W + (j - 1)] + cost;
-            int32_t deleteScore = M[(i - 1) * W + j] + gap;
-            int32_t insertScore = M[i * W + (j - 1)] + gap;
-            int32_t best = matchScore;
-            if (deleteScore > best) best = deleteScore;
-            if (insertScore > best) best = insertScore;
-            M[i * W + j] = best;
+            const int32_t above = line[j];     /* V(i-1, j) */
+            int32_t v = corner + sim[(int64_t)A[i - 1] * alphabet + B[j - 1]];
+            const int32_t a_gapped = above + gap;
+            const int32_t b_gapped = left + gap;
+            if (a_gapped > v) v = a_gapped;
+            if (b_gapped > v) v = b_gapped;
+            line[j] = v;
+            corner = above;
+            left = v;
         }
+        if (table) memcpy(table + i * (lb + 1), line, row_bytes);
     }
-    /* the bottom-right field holds the optimal score */
-    return M[la * W + lb];
+    return line[lb];
 }
 
-/* Convenience wrapper that allocates its own matrix. */
+/* score(A, B); `line` needs lb+1 int32. */
+int32_t orc_score(const uint8_t *A, int64_t la, const uint8_t *B, int64_t lb,
+                  const int32_t *sim, int32_t alphabet, int32_t gap, int32_t *line)
+{
+    return prefix_scores(A, la, B, lb, sim, alphabet, gap, line, NULL);
+}
+
+/* score(A, B) with its own row buffer. */
 int32_t orc_score1(const uint8_t *A, int64_t la, const uint8_t *B, int64_t lb,
                    const int32_t *sim, int32_t alphabet, int32_t gap)
 {
-    int32_t *M = (int32_t *)malloc(sizeof(int32_t) * (size_t)((la + 1) * (lb + 1)));
-    if (!M) return INT32_MIN;
-    int32_t s = orc_score(A, la, B, lb, sim, alphabet, gap, M);
-    free(M);
+    int32_t *line = (int32_t *)malloc(sizeof(int32_t) * (size_t)(lb + 1));
+    if (!line) return INT32_MIN;
+    int32_t s = orc_score(A, la, B, lb, sim, alphabet, gap, line);
+    free(line);
     return s;
 }
 
-/* Full score matrix for one pair (for checking worked examples). */
+/* The whole table V for one pair (to check worked examples cell by cell);
+ * M holds (la+1)*(lb+1) int32, row-major. */
 void orc_matrix(const uint8_t *A, int64_t la, const uint8_t *B, int64_t lb,
                 const int32_t *sim, int32_t alphabet, int32_t gap, int32_t *M)
 {
-    (void)orc_score(A, la, B, lb, sim, alphabet, gap, M);
+    int32_t *line = (int32_t *)malloc(sizeof(int32_t) * (size_t)(lb + 1));
+    if (!line) return;
+    (void)prefix_scores(A, la, B, lb, sim, alphabet, gap, line, M);
+    free(line);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -122,13 +148,32 @@ static uint64_t row_start(int64_t n, int64_t r)
 
 typedef struct { int32_t score; int32_t index; } entry_t;
 
-/* (score descending, index ascending) */
-static int entry_cmp(const void *x, const void *y)
+/* Does (s, j) come before entry e in a neighbour list?  Higher score first;
+ * on equal scores the lower index first. */
+static int comes_before(int32_t s, int32_t j, const entry_t *e)
 {
-    const entry_t *a = (const entry_t *)x, *b = (const entry_t *)y;
-    if (a->score != b->score) return a->score > b->score ? -1 : 1;
-    if (a->index != b->index) return a->index < b->index ? -1 : 1;
-    return 0;
+    if (s != e->score) return s > e->score;
+    return j < e->index;
+}
+
+/* Offer (s, j) to `list`, which holds the *len best entries offered so far in
+ * list order (at most k).  A full list keeps (s, j) only if it comes before
+ * the last entry, which then drops out. */
+static void list_offer(entry_t *list, int32_t k, int32_t *len, int32_t s, int32_t j)
+{
+    int32_t p;
+    if (*len < k) {
+        p = (*len)++;
+    } else {
+        if (k == 0 || !comes_before(s, j, &list[k - 1])) return;
+        p = k - 1;
+    }
+    while (p > 0 && comes_before(s, j, &list[p - 1])) {
+        list[p] = list[p - 1];
+        --p;
+    }
+    list[p].score = s;
+    list[p].index = j;
 }
 
 enum { JOB_TRIANGLE = 1, JOB_PAIRS = 2, JOB_TOPK = 3, JOB_QUERY = 4 };
@@ -136,9 +181,8 @@ enum { JOB_TRIANGLE = 1, JOB_PAIRS = 2, JOB_TOPK = 3, JOB_QUERY = 4 };
 static void *worker(void *arg)
 {
     job_t *J = (job_t *)arg;
-    int64_t L = J->max_len + 1;
-    int32_t *M = (int32_t *)malloc(sizeof(int32_t) * (size_t)(L * L));
-    entry_t *all = NULL;
+    int32_t *M = (int32_t *)malloc(sizeof(int32_t) * (size_t)(J->max_len + 1));
+    entry_t *list = NULL;
     if (!M) { J->failed = 1; return NULL; }
 
     if (J->kind == JOB_TRIANGLE) {
@@ -164,33 +208,32 @@ static void *worker(void *arg)
         }
     } else if (J->kind == JOB_TOPK || J->kind == JOB_QUERY) {
         int64_t rows = J->kind == JOB_TOPK ? J->r1 - J->r0 : J->nq;
-        all = (entry_t *)malloc(sizeof(entry_t) * (size_t)(J->n > 0 ? J->n : 1));
-        if (!all) { J->failed = 1; free(M); return NULL; }
+        list = (entry_t *)malloc(sizeof(entry_t) * (size_t)(J->k > 0 ? J->k : 1));
+        if (!list) { J->failed = 1; free(M); return NULL; }
         for (int64_t t = J->tid; t < rows; t += J->nthreads) {
             int64_t i = J->kind == JOB_TOPK ? J->r0 + t : t;
             int64_t la; const uint8_t *A;
             if (J->kind == JOB_TOPK) A = word_ptr(J->sym, J->off, i, &la);
             else A = word_ptr(J->qsym, J->qoff, i, &la);
-            int64_t cnt = 0;
+            int32_t len = 0;
             for (int64_t j = 0; j < J->n; ++j) {
                 if (J->kind == JOB_TOPK && j == i) continue;   /* no self-loops */
                 int64_t lb; const uint8_t *B = word_ptr(J->sym, J->off, j, &lb);
                 int32_t s = orc_score(A, la, B, lb, J->sim, J->alphabet, J->gap, M);
-                all[cnt].score = s; all[cnt].index = (int32_t)j; ++cnt;
+                list_offer(list, J->k, &len, s, (int32_t)j);
                 if (J->hist && J->kind == JOB_TOPK && j > i) {
                     int64_t b = (int64_t)s - J->hist_lo;
                     if (b >= 0 && b < J->hist_nbins) J->hist[b] += 1;
                 }
             }
-            qsort(all, (size_t)cnt, sizeof(entry_t), entry_cmp);
             for (int32_t r = 0; r < J->k; ++r) {
                 int64_t o = t * (int64_t)J->k + r;
-                if (r < cnt) { J->score_out[o] = all[r].score; J->index_out[o] = all[r].index; }
+                if (r < len) { J->score_out[o] = list[r].score; J->index_out[o] = list[r].index; }
                 else { J->score_out[o] = INT16_MIN; J->index_out[o] = -1; }
             }
         }
     }
-    free(all);
+    free(list);
     free(M);
     return NULL;
 }

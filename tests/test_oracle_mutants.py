@@ -18,19 +18,24 @@ import test_oracle_pins as pins
 SRC = os.path.join(os.path.dirname(oracle.__file__), "nw_oracle.c")
 
 MUTANTS = {
-    "first_column_not_gapped": ("M[i * W + 0] = gap * (int32_t)i;", "M[i * W + 0] = 0;"),
-    "first_row_wrong_sign": ("M[0 * W + j] = gap * (int32_t)j;", "M[0 * W + j] = -gap * (int32_t)j;"),
-    "diag_wrong_index": ("M[(i - 1) * W + (j - 1)] + cost", "M[(i - 1) * W + j] + cost"),
-    "delete_drops_gap": ("M[(i - 1) * W + j] + gap;", "M[(i - 1) * W + j];"),
-    "insert_wrong_neighbour": ("M[i * W + (j - 1)] + gap;", "M[(i - 1) * W + (j - 1)] + gap;"),
+    "first_column_not_gapped": ("int32_t left = (int32_t)i * gap;", "int32_t left = 0;"),
+    "first_row_wrong_sign": ("line[j] = (int32_t)j * gap;", "line[j] = -(int32_t)j * gap;"),
+    "diag_uses_left_cell": ("int32_t v = corner + sim", "int32_t v = left + sim"),
+    "left_not_advanced": ("            left = v;\n", ""),
+    "corner_not_advanced": ("            corner = above;\n", ""),
+    "a_gap_drops_penalty": ("const int32_t a_gapped = above + gap;", "const int32_t a_gapped = above;"),
+    "b_gap_wrong_neighbour": ("const int32_t b_gapped = left + gap;", "const int32_t b_gapped = corner + gap;"),
     "sim_transposed": ("sim[(int64_t)A[i - 1] * alphabet + B[j - 1]]",
                        "sim[(int64_t)B[j - 1] * alphabet + A[i - 1]]"),
     "symbol_off_by_one": ("sim[(int64_t)A[i - 1] * alphabet + B[j - 1]]",
                           "sim[(int64_t)A[i % la] * alphabet + B[j - 1]]"),
-    "max_becomes_min": ("if (deleteScore > best) best = deleteScore;",
-                        "if (deleteScore < best) best = deleteScore;"),
-    "wrong_result_cell": ("return M[la * W + lb];", "return M[la * W + (lb > 0 ? lb - 1 : 0)];"),
-    "tie_break_reversed": ("return a->index < b->index ? -1 : 1;", "return a->index > b->index ? -1 : 1;"),
+    "max_becomes_min": ("if (a_gapped > v) v = a_gapped;", "if (a_gapped < v) v = a_gapped;"),
+    "wrong_result_cell": ("return line[lb];", "return line[lb > 0 ? lb - 1 : 0];"),
+    "tie_break_reversed": ("return j < e->index;", "return j > e->index;"),
+    "full_list_keeps_every_offer": ("if (k == 0 || !comes_before(s, j, &list[k - 1])) return;",
+                                    "if (k == 0) return;"),
+    "insertion_skips_shift": ("while (p > 0 && comes_before(s, j, &list[p - 1])) {",
+                              "while (p > 1 && comes_before(s, j, &list[p - 1])) {"),
     "self_loop_kept": ("if (J->kind == JOB_TOPK && j == i) continue;", ""),
     "hist_counts_both_directions": ("J->kind == JOB_TOPK && j > i)", "J->kind == JOB_TOPK && j != i)"),
     "triangle_row_start_wrong": ("- (uint64_t)(r - 1) * (uint64_t)r / 2u;", "- (uint64_t)r * (uint64_t)r / 2u;"),
