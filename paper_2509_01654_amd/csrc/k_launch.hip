@@ -87,7 +87,7 @@ const KernelTables &kernel_tables()
     return t;
 }
 
-// A launch through a fork (a stream, or a node of a graph).
+// A launch through a fork (a stream, or a node of the graph being captured).
 static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, StreamFork &fork, void **args)
 {
     if (lds > 65536) {
@@ -95,15 +95,6 @@ static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, StreamFork &
         if (e != hipSuccess) return e;
     }
     return fork.launch(fn, grid, dim3(kThreads), lds, args);
-}
-
-static hipError_t launch_dyn(const void *fn, dim3 grid, size_t lds, hipStream_t stream, void **args)
-{
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    return hipLaunchKernel(fn, grid, dim3(kThreads), args, lds, stream);
 }
 
 // Row of pair index idx in the row-major triangle of n words: the largest u
@@ -230,7 +221,7 @@ hipError_t launch_edges_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64
         uint32_t rb0 = G.rb0, rbn = G.rbn;
         void *args[] = {&Vc, &Ec, &ib, &ie, &rb0, &rbn, &chunks, &rpc};
         hipError_t e = launch_dyn(tab.edges[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
-                                  edges_lds_bytes(LA, V.alphabet, V.CB), fork.next(), args);
+                                  edges_lds_bytes(LA, V.alphabet, V.CB), fork, args);
         if (e != hipSuccess) return e;
     }
     return fork.end();
@@ -284,7 +275,7 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
     if (h_maxrp[0] != 0) {   // empty row words: score gap * lb, the register-row kernel of length 0
         uint32_t one = 1, all = 0xFFFFFFFFu;
         void *args[] = {&Vc, &ib, &ie, &po, &ok, &es, &rb0, &rbn, &one, &all};
-        hipError_t e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), fork.next(), args);
+        hipError_t e = launch_dyn(tab.tri[0], dim3(G.blocks), tri_lds_bytes(0, V.alphabet, V.CB), fork, args);
         if (e != hipSuccess) return e;
     }
     for (int c = 0; c < kDiagClasses; ++c) {
@@ -305,8 +296,7 @@ hipError_t launch_triangle_diag(const DevVocab &V, const uint32_t *h_maxrp, cons
         const size_t lds = diag_lds_bytes(R, V.alphabet, V.CB);
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        e = hipLaunchKernel(fn, dim3((uint32_t)((uint64_t)G.blocks * chunks)), dim3(kDiagThreads), args, lds,
-                            fork.next());
+        e = fork.launch(fn, dim3((uint32_t)((uint64_t)G.blocks * chunks)), dim3(kDiagThreads), lds, args);
         if (e != hipSuccess) return e;
     }
     return fork.end();
@@ -341,7 +331,7 @@ hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_of
         Q.partial = partial;
         void *args[] = {&Q};
         const dim3 grid((np + rpw - 1) / rpw, nsplit);
-        hipError_t e = launch_dyn(tab.query[LA], grid, query_lds_bytes(LA, V.alphabet, k), fork.next(), args);
+        hipError_t e = launch_dyn(tab.query[LA], grid, query_lds_bytes(LA, V.alphabet, k), fork, args);
         if (e != hipSuccess) return e;
     }
     return fork_streams ? fork.end() : hipSuccess;
@@ -379,7 +369,7 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
                          topk_lds_bytes(LA, V.alphabet, T.nbins, 1, V.CB) <= kMaxLdsBytes;
         void *args[] = {&Vc, &Tc};
         hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs),
-                                  topk_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), fork.next(), args);
+                                  topk_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), fork, args);
         if (e != hipSuccess) return e;
     }
     return fork.end();

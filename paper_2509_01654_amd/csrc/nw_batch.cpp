@@ -10,8 +10,8 @@
 // per non-empty class] into a hipGraph once; each run replays it.
 //
 // Class width 0 is the other form: every dictionary's launches (as
-// nw_all_pairs_scores issues them), spread over one fork of library streams
-// when eager, or built into a graph as kernel nodes without dependencies.
+// nw_all_pairs_scores issues them), spread over one fork of concurrent chains
+// (library streams when eager, chains of kernel nodes inside the capture).
 //
 // Autotuner: times candidate (class width, workgroups per CU, pairs per item)
 // settings on the batch itself and caches the best per device and workload
@@ -175,13 +175,48 @@ struct nw_batch {
             int kind = out_kind;
             uint32_t nn = n;
             void *args[] = {&vocabs, &it, &nn, &ctr, &outs, &kind};
-            if ((e = hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, fork.next())) != hipSuccess) return e;
+            if ((e = fork.launch(fn, dim3(grid), dim3(kThreads), lds, args)) != hipSuccess) return e;
         }
         return fork.end();
     }
 };
 
 extern "C" {
+
+int nw_all_pairs_scores_batched(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, nw_dtype dt,
+                                void *hip_stream)
+{
+    if (!v || !d_outs) return fail(NW_EINVAL, "NULL argument");
+    if (nv == 0) return ok();
+    for (uint32_t i = 0; i < nv; ++i) {
+        int rc = check_triangle_args(v[i], 0, v[i] ? v[i]->num_pairs : 0, dt, d_outs[i]);
+        if (rc) return fail(rc, "dictionary %u: %s", i, nw_last_error());
+        if (v[i]->device != v[0]->device) return fail(NW_EINVAL, "dictionary %u is on another device", i);
+    }
+    DeviceScope scope(v[0]->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int kind = dt == NW_I8 ? OUT_I8 : OUT_I16;
+    // dictionaries with words past the register-row limit first, each on the
+    // anti-diagonal kernel's own fork; then the register-row launches of all
+    // others share one fork, so one dictionary's tail overlaps the next one's
+    // start (forks follow each other, never interleave)
+    hipError_t e = hipSuccess;
+    for (uint32_t i = 0; i < nv && e == hipSuccess; ++i)
+        if (v[i]->max_len > (uint32_t)kMaxLen)
+            e = launch_triangle_diag(v[i]->dev, v[i]->h_maxrp.data(), v[i]->h_maxdp, 0, v[i]->num_pairs, kind,
+                                     d_outs[i], st);
+    if (e != hipSuccess) return dev_fail(e, "launching the batched triangles");
+    StreamFork fork(st);
+    e = fork.begin();
+    for (uint32_t i = 0; i < nv && e == hipSuccess; ++i)
+        if (v[i]->max_len <= (uint32_t)kMaxLen)
+            e = launch_triangle_tiled(v[i]->dev, v[i]->h_maxrp.data(), 0, v[i]->num_pairs, kind, d_outs[i], st,
+                                      nullptr, &fork);
+    const hipError_t e2 = fork.end();
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return dev_fail(e, "launching the batched triangles");
+    return ok();
+}
 
 int nw_batch_workspace_bytes(const nw_vocab *const *v, uint32_t nv, const nw_batch_options *opt, uint64_t *bytes)
 {
@@ -234,23 +269,13 @@ int nw_batch_create(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, 
         if (e == hipSuccess) e = hipStreamSynchronize(B->cap);
     }
     if (e == hipSuccess && opt->use_graph) {
-        if (B->plan.width == 0) {
-            // the tiled form's graph is built node by node: every launch is a
-            // kernel node with no dependencies, so they overlap on replay
-            e = hipGraphCreate(&B->graph, 0);
-            if (e == hipSuccess) {
-                StreamFork nodes(B->graph);
-                for (size_t i = 0; i < B->v.size() && e == hipSuccess; ++i)
-                    e = launch_triangle_tiled(B->v[i]->dev, B->v[i]->h_maxrp.data(), 0, B->v[i]->num_pairs,
-                                              B->out_kind, B->outs[i], nullptr, nullptr, &nodes);
-            }
-        } else {
-            e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                hipError_t e2 = B->enqueue(B->cap);
-                e = hipStreamEndCapture(B->cap, &B->graph);
-                if (e2 != hipSuccess) e = e2;
-            }
+        // one capture of a run; the fork inside it adds its launches to the
+        // capture's graph as chains of kernel nodes
+        e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = B->enqueue(B->cap);
+            e = hipStreamEndCapture(B->cap, &B->graph);
+            if (e2 != hipSuccess) e = e2;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
     }
@@ -344,6 +369,7 @@ int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs
         }
     }
     hipStream_t s = (hipStream_t)hip_stream;
+    if (int rc = refuse_capture(s, "nw_batch_autotune")) return rc;
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -373,8 +399,8 @@ int nw_batch_autotune(const nw_vocab *const *v, uint32_t nv, void *const *d_outs
     float cur_ms = 0;
     int rc = time_one(cur, cur_ms);
     const uint32_t widths[] = {0, 1, 8}, wgs[] = {2, 4, 8}, ppi[] = {16, 64, 0};
-    // the tiled form launched eagerly (its launches overlap on forked streams,
-    // which a captured graph does not do)
+    // the tiled form launched eagerly (its launches overlap on forked
+    // library streams; the captured form replays the same chains as a graph)
     if (!rc) {
         const nw_batch_options o{0, 1, 0, 0};
         float ms = 0;
