@@ -24,6 +24,16 @@
  *   stream has been synchronised.  An nw_vocab must outlive every call that
  *   uses it and every kernel those calls enqueued.
  * - Word i is h_symbols[h_offsets[i] .. h_offsets[i+1]).  Lengths may be 0.
+ * - Graph capture: the triangle calls (nw_all_pairs_scores and its forms,
+ *   nw_all_pairs_scores_batched), nw_all_pairs_edges, nw_batch_run and
+ *   nw_ego_network may be enqueued on a stream that is being captured into a
+ *   hipGraph; their independent launches become parallel chains of kernel
+ *   nodes of the capture, and no memset, event or host callback enters it.
+ *   The calls that wait for the device, read results back, copy from
+ *   pageable host memory or run host callbacks (nw_load_vocab,
+ *   nw_all_pairs_topk, nw_all_pairs_topk_async, nw_topk_finish, nw_query,
+ *   nw_export_triangle, nw_graph_csr, nw_batch_autotune) return NW_EINVAL on
+ *   a capturing stream, before enqueuing anything.
  */
 #ifndef NW_H
 #define NW_H
@@ -119,6 +129,21 @@ int nw_score_bounds(const nw_vocab *v, int32_t *lo, int32_t *hi);
  * NW_ERANGE (the score bounds do not fit dt), NW_EDEVICE. */
 int nw_all_pairs_scores(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, nw_dtype dt,
                         void *d_out, void *hip_stream);
+
+/* The whole triangles of nv dictionaries in one call: d_outs[i] receives
+ * dictionary v[i]'s scores exactly as nw_all_pairs_scores with the range
+ * [0, E_i) writes them (row-major, dtype dt).  The register-row launches of
+ * all dictionaries are enqueued as one set of concurrent chains, so one
+ * dictionary's tail overlaps the next one's start; dictionaries with words
+ * longer than 48 take the anti-diagonal kernel.  Needs no workspace.  This is
+ * the one-call batched form; the nw_batch_* calls below plan the same work
+ * once (persistent work queues or these launches, optionally as a replayed
+ * hipGraph) and let the autotuner choose.  Every dictionary must live on the
+ * same device.  Errors: those of nw_all_pairs_scores for any dictionary
+ * (the message names it), NW_EINVAL (NULL arrays, dictionaries on different
+ * devices), NW_EDEVICE. */
+int nw_all_pairs_scores_batched(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, nw_dtype dt,
+                                void *hip_stream);
 
 /* The same scores computed by the intra-pair anti-diagonal kernel: 16 lanes
  * per pair walk the score matrix by anti-diagonals (the stencil
@@ -221,12 +246,35 @@ int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes);
  * unordered pairs {i, j} with score lo + b (bounds from nw_score_bounds): the
  * histogram of raw edge weights of Section 5.  Every unordered pair is scored
  * once.  d_ws: nw_topk_workspace_bytes() bytes, 256-byte aligned, caller-owned.
- * Synchronous: returns once the results are complete on hip_stream.
+ * Synchronous: returns once the results are complete on hip_stream.  It has
+ * to wait: a word's candidates are gathered into a list of fixed capacity,
+ * and the few words whose list overflowed are recomputed exactly by a second
+ * pass whose size (the number of such words and their ids) only the device
+ * knows after the main pass.  nw_all_pairs_topk = nw_all_pairs_topk_async
+ * followed by nw_topk_finish.
  * Errors: NW_EINVAL (k outside 1..63, asymmetric similarity, words longer
- * than 48 symbols, NULL or misaligned buffers), NW_ENOMEM (workspace too
- * small), NW_EDEVICE. */
+ * than 48 symbols, NULL or misaligned buffers, a capturing stream), NW_ENOMEM
+ * (workspace too small), NW_EDEVICE. */
 int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist,
                       void *d_ws, uint64_t ws_bytes, void *hip_stream);
+
+/* Enqueue-only form: the threshold pre-pass, the main pass (histogram
+ * included) and the selection are enqueued on hip_stream and the call
+ * returns.  Once the stream has synchronised, d_hist is complete and every
+ * list is exact except those of words whose candidate list overflowed;
+ * nw_topk_finish, called next with the same dictionary, k, outputs and
+ * workspace, recomputes those and must precede any use of the lists.  One
+ * pass per dictionary may be pending at a time.  Same arguments and errors
+ * as nw_all_pairs_topk. */
+int nw_all_pairs_topk_async(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist,
+                            void *d_ws, uint64_t ws_bytes, void *hip_stream);
+
+/* Complete the pass nw_all_pairs_topk_async enqueued: waits for hip_stream,
+ * reads the overflow count, recomputes the overflowed words' lists exactly
+ * (blocking) and records the phase times.  NW_EINVAL if no pass is pending
+ * on this dictionary; otherwise the errors of nw_all_pairs_topk. */
+int nw_topk_finish(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes,
+                   void *hip_stream);
 
 /* GPU time of the three phases of the last completed nw_all_pairs_topk call
  * on this dictionary, from HIP events recorded on its stream: the probe
@@ -246,30 +294,46 @@ int nw_query_workspace_bytes(const nw_vocab *v, uint64_t n_q, uint64_t q_symbols
  * its k best dictionary neighbours over all dictionary words d (no
  * self-exclusion), A = the query word: d_score[q*k + r], d_index[q*k + r].
  * The similar-word lookup the paper envisions (Section 6).  Enqueued on
- * hip_stream; the host arrays may be reused when the call returns.
- * Errors: NW_EINVAL (k outside 1..64, bad query words), NW_ERANGE (query
- * scores could leave int16), NW_ENOMEM (workspace too small). */
+ * hip_stream; the host arrays may be reused when the call returns (the
+ * library's host image of the batch is released by a host callback on the
+ * stream once its copy is done, which is why the call refuses a capturing
+ * stream).
+ * Errors: NW_EINVAL (k outside 1..64, bad query words, a capturing stream),
+ * NW_ERANGE (query scores could leave int16), NW_ENOMEM (workspace too
+ * small). */
 int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_offsets, uint64_t n_q, uint32_t k,
              int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes, void *hip_stream);
 
 /* ---------------------------------------------------------------------------
- * Query server: continuous batching over a resident dictionary.
- * A scheduler thread admits the oldest waiting queries (up to max_batch) into
- * any free slot; each slot has its own stream, workspace region and pinned
+ * Query server: continuous batching over a resident dictionary, admitted by
+ * memory.  A scheduler thread admits the oldest waiting queries (up to
+ * max_batch) into any free slot; each slot has its own stream and pinned
  * buffers, so batches overlap on the device and requests arriving meanwhile
- * start as soon as a slot (and its memory) frees up.  A query's result is the
- * one nw_query gives for it alone.
+ * start as soon as a slot and memory free up.  The device workspace is a pool:
+ * a batch of q queries reserves the bytes its own query workspace and results
+ * need and returns them on completion; a batch is shrunk to what the largest
+ * free range holds, and when not even one query fits, admission waits for a
+ * running batch (back-pressure).  A query's result is the one nw_query gives
+ * for it alone, whatever batch or memory it ran in.  Serving is the online
+ * similar-word lookup the paper envisions (Section 6).
  * ------------------------------------------------------------------------- */
 typedef struct nw_server nw_server;
 
-/* Device workspace bytes of a server (num_slots regions).  k 1..64,
+/* Device workspace bytes at which no admission ever waits for memory:
+ * num_slots times the largest batch (of 1..max_batch queries).  k 1..64,
  * max_batch 1..4096, num_slots 1..16. */
 int nw_server_workspace_bytes(const nw_vocab *v, uint32_t k, uint32_t max_batch, uint32_t num_slots,
                               uint64_t *bytes);
 
-/* Start a server.  d_ws (caller-owned, 256-byte aligned) must stay valid,
- * like v, until nw_server_destroy returns.  The server creates its own
- * streams, events and pinned host buffers. */
+/* The smallest workspace a server accepts: one batch of one query. */
+int nw_server_min_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes);
+
+/* Start a server.  d_ws (caller-owned, 256-byte aligned, ws_bytes between
+ * nw_server_min_workspace_bytes and nw_server_workspace_bytes; more is not
+ * used) is the memory pool; it must stay valid, like v, until
+ * nw_server_destroy returns.  The server creates its own streams, events and
+ * pinned host buffers.  Errors: NW_EINVAL, NW_ENOMEM (ws_bytes below the
+ * minimum), NW_EDEVICE. */
 int nw_server_create(const nw_vocab *v, uint32_t k, uint32_t max_batch, uint32_t num_slots, void *d_ws,
                      uint64_t ws_bytes, nw_server **out);
 
@@ -294,31 +358,47 @@ int nw_server_replay(nw_server *s, const uint8_t *h_symbols, const uint64_t *h_o
 /* Batches and queries completed so far. */
 int nw_server_stats(nw_server *s, uint64_t *batches, uint64_t *queries);
 
-/* Finish the queued and running batches and release the server. */
+/* Memory admission so far: the pool size in use, the most bytes reserved at
+ * once, and how many admitted batches had waited or were shrunk because the
+ * pool was short.  Any pointer may be NULL. */
+int nw_server_memory_stats(nw_server *s, uint64_t *pool_bytes, uint64_t *peak_bytes, uint64_t *waits);
+
+/* Test hook: the next batch the scheduler admits fails on the host before
+ * anything of it is enqueued, as a failed launch would.  The server then
+ * admits nothing more: queued queries are dropped, submit and poll return
+ * NW_EDEVICE, and nw_server_destroy still returns once the batches in flight
+ * have drained. */
+int nw_server_inject_failure(nw_server *s);
+
+/* Finish the queued and running batches and release the server (after an
+ * error: the running batches only). */
 void nw_server_destroy(nw_server *s);
 
 /* The server clock (steady, nanoseconds). */
 int64_t nw_clock_ns(void);
 
 /* ---------------------------------------------------------------------------
- * Batched form: the triangles of many dictionaries (each with its own words;
- * every dictionary symmetric) in one graph-captured sequence of launches.
+ * Batched form, planned: the triangles of many dictionaries (each with its own
+ * words; every dictionary symmetric) in one graph-captured sequence of
+ * launches.  nw_batch_create plans once and nw_batch_run replays; together
+ * they take the place of the one-call nw_all_pairs_scores_batched above when
+ * the same dictionaries are scored repeatedly (the persistent form needs a
+ * workspace for its work queues, which the one-call form does without).
  * Persistent form: work items (dictionary, block pair, row length, chunk of
  * row pairs) are ordered heaviest first inside row-length classes; one
  * persistent kernel per class drains its queue.  Tiled form (class_width 0):
  * every dictionary's per-length tiled launches, as nw_all_pairs_scores issues
- * them, on forked library streams.  nw_batch_autotune times both.
+ * them, spread over concurrent chains (library streams when eager, chains of
+ * kernel nodes in the graph).  nw_batch_autotune times both.
  * ------------------------------------------------------------------------- */
 typedef struct {
     uint32_t class_width;     /* 1: one persistent kernel per row length; 8: classes of 8 lengths;
                                  0: no persistent kernels -- every dictionary's per-length tiled
-                                 launches, spread over library streams (wg_per_cu and
+                                 launches, spread over concurrent chains (wg_per_cu and
                                  pairs_per_item unused) */
     uint32_t wg_per_cu;       /* persistent workgroups per compute unit (>= 1) */
     uint32_t pairs_per_item;  /* row pairs per work item (0 = all of a block and length) */
-    uint32_t use_graph;       /* 1: capture once into a hipGraph and replay; 0: launch eagerly.
-                                 Launches that are spread over library streams when
-                                 eager stay on one stream inside a capture. */
+    uint32_t use_graph;       /* 1: capture once into a hipGraph and replay; 0: launch eagerly */
 } nw_batch_options;
 
 typedef struct nw_batch nw_batch;

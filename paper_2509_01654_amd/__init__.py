@@ -7,8 +7,10 @@ There is no fallback: if the library has not been built, every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -75,6 +77,9 @@ def load_library(path: str = LIB_PATH):
         "nw_all_pairs_scores_diag": (ctypes.c_int, [P, u64, u64, ctypes.c_int, P, P]),
         "nw_topk_workspace_bytes": (ctypes.c_int, [P, u32, ctypes.POINTER(u64)]),
         "nw_all_pairs_topk": (ctypes.c_int, [P, u32, P, P, P, P, u64, P]),
+        "nw_all_pairs_topk_async": (ctypes.c_int, [P, u32, P, P, P, P, u64, P]),
+        "nw_topk_finish": (ctypes.c_int, [P, u32, P, P, P, u64, P]),
+        "nw_all_pairs_scores_batched": (ctypes.c_int, [P, u32, P, ctypes.c_int, P]),
         "nw_query_workspace_bytes": (ctypes.c_int, [P, u64, u64, u32, ctypes.POINTER(u64)]),
         "nw_topk_phase_times": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                                ctypes.POINTER(ctypes.c_float)]),
@@ -94,6 +99,9 @@ def load_library(path: str = LIB_PATH):
         "nw_server_poll": (ctypes.c_int, [P, u32, ctypes.c_int32, P, P, P, P, ctypes.POINTER(u32)]),
         "nw_server_replay": (ctypes.c_int, [P, P, P, u64, P, P, P, P]),
         "nw_server_stats": (ctypes.c_int, [P, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "nw_server_min_workspace_bytes": (ctypes.c_int, [P, u32, ctypes.POINTER(u64)]),
+        "nw_server_memory_stats": (ctypes.c_int, [P, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "nw_server_inject_failure": (ctypes.c_int, [P]),
         "nw_server_destroy": (None, [P]),
         "nw_clock_ns": (ctypes.c_int64, []),
         "nw_batch_workspace_bytes": (ctypes.c_int, [P, u32, ctypes.POINTER(_BatchOptions), ctypes.POINTER(u64)]),
@@ -116,6 +124,26 @@ def load_library(path: str = LIB_PATH):
 def _check(rc: int):
     if rc != NW_OK:
         raise NwError(rc, _lib.nw_last_error().decode())
+
+
+# Objects that own library resources.  At interpreter exit they are released
+# in dependency order (servers, then batches, then dictionaries) by an atexit
+# handler, while the HIP runtime and this module are still intact; each object
+# keeps its own reference to the library, so a late __del__ never needs the
+# module's globals.
+_live = weakref.WeakSet()
+_CLOSE_ORDER = {"Server": 0, "Batch": 1, "Vocab": 2}
+
+
+def _close_all():
+    for obj in sorted(list(_live), key=lambda o: _CLOSE_ORDER.get(type(o).__name__, 3)):
+        try:
+            obj.close()
+        except Exception:  # nothing useful can be done with an error at exit
+            pass
+
+
+atexit.register(_close_all)
 
 
 def _stream_handle(stream):
@@ -210,6 +238,8 @@ class Vocab:
                                  ctypes.c_void_p(self.mem.data_ptr()), nbytes, _stream_handle(stream),
                                  ctypes.byref(handle)))
         self._h = handle
+        self._lib = lib
+        _live.add(self)
         self.device = self.mem.device
         N, L, E, C = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib.nw_vocab_info(self._h, ctypes.byref(N), ctypes.byref(L), ctypes.byref(E), ctypes.byref(C)))
@@ -218,11 +248,15 @@ class Vocab:
         _check(lib.nw_score_bounds(self._h, ctypes.byref(lo), ctypes.byref(hi)))
         self.bounds = (lo.value, hi.value)
 
+    def close(self):
+        """Release the host descriptor (the device memory is a torch tensor)."""
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h is not None and h.value and lib is not None:
+            lib.nw_free_vocab(h)
+        self._h = None
+
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib is not None:
-            _lib.nw_free_vocab(h)
-            self._h = None
+        self.close()
 
     def _triangle(self, fn, idx_begin, idx_end, dtype, out, stream):
         import torch
@@ -363,6 +397,23 @@ class Vocab:
                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
         return sc, ix, h
 
+    def all_pairs_topk_async(self, k: int, ws, out, stream=None):
+        """Enqueue the top-k passes and return (nw_all_pairs_topk_async); call
+        topk_finish with the same k, ws and out before using the lists."""
+        sc, ix, h = out
+        hp = ctypes.c_void_p(h.data_ptr()) if h is not None else None
+        _check(_lib.nw_all_pairs_topk_async(self._h, k, ctypes.c_void_p(sc.data_ptr()),
+                                            ctypes.c_void_p(ix.data_ptr()), hp, ctypes.c_void_p(ws.data_ptr()),
+                                            ws.numel(), _stream_handle(stream)))
+        return out
+
+    def topk_finish(self, k: int, ws, out, stream=None):
+        """Complete an enqueued top-k pass (nw_topk_finish; blocks)."""
+        sc, ix, _ = out
+        _check(_lib.nw_topk_finish(self._h, k, ctypes.c_void_p(sc.data_ptr()), ctypes.c_void_p(ix.data_ptr()),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+        return out
+
     def topk_phase_times(self):
         """(pre-pass, main pass, select) GPU milliseconds of the last all_pairs_topk."""
         a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
@@ -397,18 +448,23 @@ class Vocab:
 class Server:
     """Continuous-batching query server over a resident dictionary (nw_server_*)."""
 
-    def __init__(self, vocab: Vocab, k: int = 16, max_batch: int = 256, num_slots: int = 4):
+    def __init__(self, vocab: Vocab, k: int = 16, max_batch: int = 256, num_slots: int = 4, ws_bytes=None):
+        """ws_bytes caps the device memory pool batches are admitted against
+        (default: enough for every slot to hold a max_batch batch at once)."""
         import torch
         lib = load_library()
         self.vocab, self.k = vocab, k
         nbytes = ctypes.c_uint64()
         _check(lib.nw_server_workspace_bytes(vocab._h, k, max_batch, num_slots, ctypes.byref(nbytes)))
-        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=vocab.device)
+        size = nbytes.value if ws_bytes is None else int(ws_bytes)
+        self.ws = torch.empty(max(size, 256), dtype=torch.uint8, device=vocab.device)
         torch.cuda.synchronize(vocab.device)
         h = ctypes.c_void_p()
         _check(lib.nw_server_create(vocab._h, k, max_batch, num_slots, ctypes.c_void_p(self.ws.data_ptr()),
-                                    nbytes.value, ctypes.byref(h)))
+                                    size, ctypes.byref(h)))
         self._h = h
+        self._lib = lib
+        _live.add(self)
 
     def submit(self, symbols, tag: int, t_arrival_ns: int = 0):
         sym = np.ascontiguousarray(np.asarray(symbols, dtype=np.uint8))
@@ -443,11 +499,27 @@ class Server:
         _check(_lib.nw_server_stats(self._h, ctypes.byref(b), ctypes.byref(q)))
         return b.value, q.value
 
+    def memory_stats(self):
+        """(pool bytes, peak bytes reserved at once, batches that waited or shrank for memory)."""
+        p, k, w = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.nw_server_memory_stats(self._h, ctypes.byref(p), ctypes.byref(k), ctypes.byref(w)))
+        return p.value, k.value, w.value
+
+    def inject_failure(self):
+        """Make the next admitted batch fail on the host (tests of the error path)."""
+        _check(_lib.nw_server_inject_failure(self._h))
+
+    @staticmethod
+    def min_workspace_bytes(vocab, k: int = 16) -> int:
+        out = ctypes.c_uint64()
+        _check(load_library().nw_server_min_workspace_bytes(vocab._h, k, ctypes.byref(out)))
+        return out.value
+
     def close(self):
-        # at interpreter exit the module's library handle may already be gone
-        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
-            _lib.nw_server_destroy(self._h)
-            self._h = None
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h is not None and h.value and lib is not None:
+            lib.nw_server_destroy(h)
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -455,6 +527,25 @@ class Server:
 
 def clock_ns() -> int:
     return load_library().nw_clock_ns()
+
+
+def all_pairs_scores_batched(vocabs, dtype=None, outs=None, stream=None):
+    """Whole triangles of several dictionaries in one call (nw_all_pairs_scores_batched);
+    returns the output tensors (row-major, one per dictionary)."""
+    import torch
+    lib = load_library()
+    dtype = dtype or torch.int16
+    dt = {torch.int8: NW_I8, torch.int16: NW_I16}[dtype]
+    vocabs = list(vocabs)
+    if outs is None:
+        outs = [torch.empty(max(1, v.num_pairs), dtype=dtype, device=v.device) for v in vocabs]
+    for v, o in zip(vocabs, outs):
+        assert o.dtype == dtype and o.is_contiguous() and o.numel() >= v.num_pairs
+    nv = len(vocabs)
+    vh = (ctypes.c_void_p * max(1, nv))(*[v._h.value for v in vocabs])
+    oh = (ctypes.c_void_p * max(1, nv))(*[o.data_ptr() for o in outs])
+    _check(lib.nw_all_pairs_scores_batched(vh, nv, oh, dt, _stream_handle(stream)))
+    return outs
 
 
 class Batch:
@@ -496,6 +587,8 @@ class Batch:
         _check(lib.nw_batch_create(self._vh, nv, self._oh, self.dt, ctypes.byref(opt),
                                    ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(h)))
         self._h = h
+        self._lib = lib
+        _live.add(self)
 
     def run(self, stream=None):
         _check(_lib.nw_batch_run(self._h, _stream_handle(stream)))
@@ -507,10 +600,10 @@ class Batch:
         return items.value, launches.value
 
     def close(self):
-        # at interpreter exit the module's library handle may already be gone
-        if getattr(self, "_h", None) is not None and self._h.value and _lib is not None:
-            _lib.nw_batch_destroy(self._h)
-            self._h = None
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h is not None and h.value and lib is not None:
+            lib.nw_batch_destroy(h)
+        self._h = None
 
     def __del__(self):
         self.close()

@@ -46,6 +46,16 @@ int dev_fail(hipError_t e, const char *what)
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+int refuse_capture(hipStream_t stream, const char *call)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return dev_fail(e, call);
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(NW_EINVAL, "%s cannot be captured into a graph (the stream is capturing)", call);
+    return NW_OK;
+}
+
 // Block size: small dictionaries need many workgroups; large ones amortise
 // the per-row-pair work (profile build, barrier) over more lane words.
 int choose_block(uint64_t n)
@@ -364,6 +374,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     if (d_bytes < L.total)
         return fail(NW_ENOMEM, "d_mem holds %llu bytes; the dictionary needs %llu", (unsigned long long)d_bytes,
                     (unsigned long long)L.total);
+    if (int rc = refuse_capture((hipStream_t)hip_stream, "nw_load_vocab")) return rc;
 
     // host image of the device layout
     std::vector<uint8_t> img(L.total, 0);
@@ -663,23 +674,33 @@ int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes)
     return ok();
 }
 
-int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist, void *d_ws,
-                      uint64_t ws_bytes, void *hip_stream)
+namespace {
+
+// Arguments shared by the top-k calls: NW_OK or the error already recorded.
+int check_topk_args(const nw_vocab *v, uint32_t k, const int16_t *d_score, const int32_t *d_index, const void *d_ws,
+                    uint64_t ws_bytes, hipStream_t st, const char *call)
 {
     if (!v) return fail(NW_EINVAL, "vocab is NULL");
-    DeviceScope scope(v->device);
     if (k < 1 || k > 63) return fail(NW_EINVAL, "k = %u outside 1..63", k);
     if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
     if (v->max_len > (uint32_t)kMaxLen)
         return fail(NW_EINVAL, "top-k supports words of at most %d symbols (this dictionary has %u)", kMaxLen, v->max_len);
-    const uint64_t n = v->n;
-    const TopkWs W = topk_ws(n, k);
-    if (n > 0 && (!d_score || !d_index)) return fail(NW_EINVAL, "d_score / d_index is NULL");
+    const TopkWs W = topk_ws(v->n, k);
+    if (v->n > 0 && (!d_score || !d_index)) return fail(NW_EINVAL, "d_score / d_index is NULL");
     if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
     if (ws_bytes < W.total)
         return fail(NW_ENOMEM, "workspace holds %llu bytes; top-k needs %llu", (unsigned long long)ws_bytes,
                     (unsigned long long)W.total);
-    hipStream_t st = (hipStream_t)hip_stream;
+    return refuse_capture(st, call);
+}
+
+// The pre-pass, the two main-pass phases and the selection, enqueued on st
+// (arguments already checked, the dictionary's device current).
+int topk_enqueue(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist, void *d_ws,
+                 hipStream_t st)
+{
+    const uint64_t n = v->n;
+    const TopkWs W = topk_ws(n, k);
     const DevVocab &D = v->dev;
     const int nbins = v->hi - v->lo + 1;
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
@@ -741,14 +762,33 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
     if ((e = launch_select(cnt, lists, W.cap, (int64_t)n, (int)k, D.lo, d_score, d_index, ovf, reinterpret_cast<int32_t *>(ovf + 1), st)) != hipSuccess)
         return dev_fail(e, "launching the top-k selection");
     if ((e = hipEventRecord(vm->ev[3], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
+    vm->topk_pending = true;
+    return ok();
+}
+
+// Wait for the enqueued passes, then recompute exactly the words whose
+// candidate list overflowed (their count and ids are read back to the host).
+int topk_finish(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, void *d_ws, hipStream_t st)
+{
+    const uint64_t n = v->n;
+    const TopkWs W = topk_ws(n, k);
+    nw_vocab *vm = const_cast<nw_vocab *>(v);
+    const DevVocab &D = v->dev;
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    uint32_t *ovf = reinterpret_cast<uint32_t *>(ws + W.ovf);
+    uint64_t *lists = reinterpret_cast<uint64_t *>(ws + W.lists);
+    hipError_t e;
     // 4. words whose candidates overflowed the list: exact recomputation
     uint32_t novf = 0;
-    if ((e = hipMemcpyAsync(&novf, ovf, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return dev_fail(e, "reading the overflow count");
+    if (n > 0 && (e = hipMemcpyAsync(&novf, ovf, 4, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return dev_fail(e, "reading the overflow count");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail(e, "top-k");
     vm->last_overflow = novf;
-    for (int ph = 0; ph < 3; ++ph)
-        if ((e = hipEventElapsedTime(&vm->phase_ms[ph], vm->ev[ph], vm->ev[ph + 1])) != hipSuccess)
-            return dev_fail(e, "reading timing events");
+    if (vm->topk_pending && n > 0)
+        for (int ph = 0; ph < 3; ++ph)
+            if ((e = hipEventElapsedTime(&vm->phase_ms[ph], vm->ev[ph], vm->ev[ph + 1])) != hipSuccess)
+                return dev_fail(e, "reading timing events");
+    vm->topk_pending = false;
     if (novf == 0) return ok();
     std::vector<int32_t> words(novf);
     if ((e = hipMemcpy(words.data(), ovf + 1, 4ull * novf, hipMemcpyDeviceToHost)) != hipSuccess) return dev_fail(e, "reading overflowed words");
@@ -797,6 +837,43 @@ int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return dev_fail(e, "recomputing overflowed words");
     }
     return ok();
+}
+
+}  // namespace
+
+int nw_all_pairs_topk(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist, void *d_ws,
+                      uint64_t ws_bytes, void *hip_stream)
+{
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    DeviceScope scope(v->device);
+    int rc = check_topk_args(v, k, d_score, d_index, d_ws, ws_bytes, st, "nw_all_pairs_topk");
+    if (rc) return rc;
+    if ((rc = topk_enqueue(v, k, d_score, d_index, d_hist, d_ws, st))) return rc;
+    return topk_finish(v, k, d_score, d_index, d_ws, st);
+}
+
+int nw_all_pairs_topk_async(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, uint64_t *d_hist,
+                            void *d_ws, uint64_t ws_bytes, void *hip_stream)
+{
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    DeviceScope scope(v->device);
+    int rc = check_topk_args(v, k, d_score, d_index, d_ws, ws_bytes, st, "nw_all_pairs_topk_async");
+    if (rc) return rc;
+    return topk_enqueue(v, k, d_score, d_index, d_hist, d_ws, st);
+}
+
+int nw_topk_finish(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes,
+                   void *hip_stream)
+{
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!v) return fail(NW_EINVAL, "vocab is NULL");
+    DeviceScope scope(v->device);
+    int rc = check_topk_args(v, k, d_score, d_index, d_ws, ws_bytes, st, "nw_topk_finish");
+    if (rc) return rc;
+    if (!v->topk_pending && v->n > 0) return fail(NW_EINVAL, "no top-k pass is pending on this dictionary");
+    return topk_finish(v, k, d_score, d_index, d_ws, st);
 }
 
 int nw_topk_phase_times(const nw_vocab *v, float *prepass_ms, float *main_ms, float *select_ms)
@@ -856,6 +933,7 @@ int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_
     }
     const long lo = query_lo(v, qmax);
     if (lo < -32768) return fail(NW_ERANGE, "query scores may fall below int16");
+    if (int rc = refuse_capture((hipStream_t)hip_stream, "nw_query")) return rc;
     RowImage img = make_rows(rows);
     // one contiguous host image of the row set -> one copy; the image lives
     // until the copy has completed (freed by a host callback on the stream)

@@ -53,6 +53,7 @@ int nw_export_triangle(const nw_vocab *v, uint64_t idx_begin, uint64_t idx_end, 
     if (!fn || !h_buf) return fail(NW_EINVAL, "NULL callback or host buffer");
     if (chunk_pairs == 0) return fail(NW_EINVAL, "chunk_pairs must be at least 1");
     if ((uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be 256-byte aligned");
+    if ((rc = refuse_capture((hipStream_t)hip_stream, "nw_export_triangle"))) return rc;
     const uint64_t es = dt == NW_I8 ? 1 : 2;
     const uint64_t total = idx_end - idx_begin;
     const uint64_t nchunks = (total + chunk_pairs - 1) / chunk_pairs;

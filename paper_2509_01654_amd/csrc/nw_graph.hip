@@ -205,6 +205,7 @@ int nw_graph_csr(uint64_t n, const int32_t *d_i, const int32_t *d_j, uint64_t m,
         return fail(NW_ENOMEM, "workspace holds %llu bytes; the graph needs %llu", (unsigned long long)ws_bytes,
                     (unsigned long long)W.total);
     hipStream_t st = (hipStream_t)hip_stream;
+    if (int rc = refuse_capture(st, "nw_graph_csr")) return rc;
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
     auto *deg = reinterpret_cast<unsigned long long *>(ws + W.deg);
     auto *sums = reinterpret_cast<unsigned long long *>(ws + W.sums);

@@ -42,6 +42,7 @@ struct nw_vocab {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float phase_ms[3] = {0, 0, 0};
     uint32_t last_overflow = 0;       // words recomputed exactly by the last top-k call
+    bool topk_pending = false;        // a top-k pass was enqueued and not yet finished
     ~nw_vocab()
     {
         for (auto &e : ev)
@@ -66,6 +67,11 @@ int fail(int code, const char *fmt, ...);
 int ok();
 int dev_fail(hipError_t e, const char *what);
 uint64_t align_up(uint64_t x, uint64_t a);
+// NW_EINVAL (recorded) when `stream` is being captured into a graph: for the
+// calls that wait for the device, read results back to the host, copy from
+// pageable host memory or run host callbacks, none of which a captured graph
+// can replay.  NW_OK otherwise.
+int refuse_capture(hipStream_t stream, const char *call);
 
 // Workspace layout of one nw_query call of n_q queries (byte offsets).
 struct QueryWs {
