@@ -90,3 +90,63 @@ def test_server_rejects_bad_queries(dictionary):
     with pytest.raises(nw.NwError):
         srv.submit(np.array([40], np.uint8), tag=1)
     srv.close()
+
+
+def test_admission_by_memory_with_a_capped_pool(dictionary):
+    """A pool that holds about one small batch at a time: batches wait or
+    shrink for memory, never exceed the pool, and every result is still the
+    query's result alone."""
+    import paper_2509_01654_amd as nw
+    _report("server with a capped workspace pool")
+    v, dv = dictionary
+    k = 16
+    least = nw.Server.min_workspace_bytes(dv, k)
+    pool = 3 * least
+    srv = nw.Server(dv, k=k, max_batch=64, num_slots=4, ws_bytes=pool)
+    q = synth.query_words(400, seed=64)
+    for t in range(q.n):
+        srv.submit(q.word(t), tag=t)
+    got = {}
+    while len(got) < q.n:
+        tags, sc, ix, lat = srv.poll(256, 100000)
+        for t, s, i in zip(tags, sc, ix):
+            got[int(t)] = (s.copy(), i.copy())
+    size, peak, waits = srv.memory_stats()
+    batches, queries = srv.stats()
+    srv.close()
+    assert size <= pool and 0 < peak <= size
+    assert waits >= 1 and queries == q.n and batches >= 2
+    s1, i1 = _alone(dv, q, k)
+    for t in range(q.n):
+        np.testing.assert_array_equal(got[t][1], i1[t])
+        np.testing.assert_array_equal(got[t][0], s1[t])
+    with pytest.raises(nw.NwError) as e:
+        nw.Server(dv, k=k, max_batch=8, num_slots=1, ws_bytes=least - 256)
+    assert e.value.code == nw.NW_ENOMEM
+
+
+def test_failed_launch_stops_admission_and_destroy_returns(dictionary):
+    """A batch that fails on the host (injected before anything is enqueued):
+    the server reports the error, drops what was queued, and closing it
+    returns even though requests were still waiting."""
+    import time
+    import paper_2509_01654_amd as nw
+    _report("server error path: injected host-side failure")
+    _, dv = dictionary
+    srv = nw.Server(dv, k=8, max_batch=4, num_slots=1)
+    srv.inject_failure()
+    q = synth.query_words(64, seed=65)
+    for t in range(q.n):
+        try:
+            srv.submit(q.word(t), tag=t)
+        except nw.NwError as e:
+            assert e.code == nw.NW_EDEVICE
+            break
+    t0 = time.time()
+    with pytest.raises(nw.NwError) as e:
+        while time.time() - t0 < 30:
+            srv.poll(64, 100000)
+    assert e.value.code == nw.NW_EDEVICE and "injected" in str(e.value)
+    t1 = time.time()
+    srv.close()
+    assert time.time() - t1 < 10
