@@ -304,6 +304,20 @@ int nw_query_workspace_bytes(const nw_vocab *v, uint64_t n_q, uint64_t q_symbols
 int nw_query(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_offsets, uint64_t n_q, uint32_t k,
              int16_t *d_score, int32_t *d_index, void *d_ws, uint64_t ws_bytes, void *hip_stream);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): nw_query without a workspace
+ * argument.  Same results, arguments and errors as nw_query for the same
+ * queries and k, but the query workspace is a fixed 4 MiB device array of the
+ * library (one per device, kept until the process ends), so at most 256
+ * queries per call (NW_EINVAL beyond); the host image is built on the stack
+ * and uploaded as kernel arguments, so nothing is allocated on the device or
+ * the host, and the host arrays may be reused when the call returns.  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (two streams, two threads) race and must be serialised by the
+ * caller. */
+int nw_query_noalloc(const nw_vocab *v, const uint8_t *h_q_symbols, const uint64_t *h_q_offsets, uint64_t n_q,
+                     uint32_t k, int16_t *d_score, int32_t *d_index, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Query server: continuous batching over a resident dictionary, admitted by
  * memory.  A scheduler thread admits the oldest waiting queries (up to

@@ -46,6 +46,7 @@ def _units():
         ("nw_graph", os.path.join(CSRC, "nw_graph.hip"), []),
         ("k_peak", os.path.join(CSRC, "k_peak.hip"), []),
         ("k_launch", os.path.join(CSRC, "k_launch.hip"), []),
+        ("nw_noalloc", os.path.join(CSRC, "nw_noalloc.hip"), []),
     ]
     for lo, hi in _la_splits():
         units.append((f"k_inst_{lo}_{hi}", os.path.join(CSRC, "k_inst.hip"),
