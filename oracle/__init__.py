@@ -31,18 +31,42 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nw_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# NW_ORACLE_LIB names another build of the same source (the sanitizer build of
+# the CPU tests); by default oracle/liboracle.so
+_LIB = os.environ.get("NW_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
 _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc into oracle/liboracle.so."""
+    """Compile the C oracle with gcc into oracle/liboracle.so (or NW_ORACLE_LIB)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC])
+        flags = ["-O2"]
+        if _LIB == _SAN_LIB:
+            flags = _SAN_FLAGS
+        subprocess.check_call(["gcc"] + flags + ["-std=c11", "-fPIC", "-shared", "-pthread",
+                                                 "-Wall", "-Wextra", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+# AddressSanitizer + UndefinedBehaviorSanitizer, every report fatal.
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def build_sanitized() -> str:
+    """Compile the C oracle with AddressSanitizer and UBSan into oracle/liboracle_san.so.
+
+    A process loads it with the sanitizer runtime preloaded
+    (LD_PRELOAD=$(gcc -print-file-name=libasan.so)) and NW_ORACLE_LIB set to
+    the returned path."""
+    if not os.path.exists(_SAN_LIB) or os.path.getmtime(_SAN_LIB) < os.path.getmtime(_SRC):
+        tmp = _SAN_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc"] + _SAN_FLAGS + ["-std=c11", "-fPIC", "-shared", "-pthread",
+                                                      "-Wall", "-Wextra", "-o", tmp, _SRC])
+        os.replace(tmp, _SAN_LIB)
+    return _SAN_LIB
 
 
 def _load():

@@ -15,7 +15,9 @@ import weakref
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnw.so")
+# NW_LIBRARY names another build of the same library (the host-sanitizer build
+# of the CPU tests); by default the in-tree libnw.so
+LIB_PATH = os.environ.get("NW_LIBRARY") or os.path.join(_HERE, "libnw.so")
 
 NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOMEM, NW_EDEVICE, NW_ESTOPPED = 0, -1, -2, -3, -4, -5
 NW_I8, NW_I16 = 1, 2

@@ -86,5 +86,59 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     return LIB
 
 
+# Host code with AddressSanitizer + UBSan (every report fatal).  Each flag is
+# scoped to the host compilation: device code is never built with them.
+HOST_SAN_FLAGS = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=all",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+HOST_SAN_LIB = os.path.join(OUT_DIR, "libnw_hostsan.so")
+# the units that hold only host code: argument checks, layouts, schedulers
+HOST_UNITS = ["nw_api", "nw_server", "nw_batch", "nw_export"]
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """libnw with its host-only units built under AddressSanitizer and UBSan.
+
+    The other units' objects come from the last build() (run it first).  A
+    process loads the result with the sanitizer runtime preloaded
+    (LD_PRELOAD = hipcc's libclang_rt.asan-x86_64.so) and NW_LIBRARY set to
+    the returned path."""
+    units = {u[0]: u for u in _units()}
+    objs = []
+    for name, src, extra in units.values():
+        obj = os.path.join(OUT_DIR, name + ".o")
+        if name in HOST_UNITS:
+            obj = os.path.join(OUT_DIR, name + ".hostsan.o")
+            cmd = [HIPCC] + DEVICE_FLAGS + HOST_SAN_FLAGS + extra + ["-c", src, "-o", obj]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        elif not os.path.exists(obj):
+            raise RuntimeError(f"{obj} is missing: run build() first")
+        objs.append(obj)
+    tmp = HOST_SAN_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address,undefined",
+           "-Xarch_host", "-shared-libsan", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, HOST_SAN_LIB)
+    if verbose:
+        print(f"built {HOST_SAN_LIB}", file=sys.stderr)
+    return HOST_SAN_LIB
+
+
+def asan_runtime() -> str:
+    """hipcc's shared AddressSanitizer runtime (to preload into Python)."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+        hits = glob.glob("/opt/rocm*/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+        if not hits:
+            raise RuntimeError("no libclang_rt.asan-x86_64.so found")
+        path = hits[0]
+    return path
+
+
 if __name__ == "__main__":
     build()
