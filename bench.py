@@ -63,11 +63,11 @@ def roofline(cells: float, seconds: float, kernel: str, traffic=None, algorithmi
 # HBM bytes of the main pass from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, kept in
 # this summary together with the SHA-256 of the sources the kernel was built from
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "topk_main_paper600k_counters.md")
-MAIN_PASS_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "nw_topk.h", "k_topk.h", "k_query.h",
+MAIN_PASS_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "nw_topk.h", "k_topk.h", "k_topk_code.h", "k_query.h",
                      "k_launch.hip", "k_inst.hip", "nw_api.cpp"]
-# the same for the 50,000-word int8 triangle (k_tri_tiled)
+# the same for the 50,000-word int8 triangle (k_tri_code)
 TRI_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "tri_tiled_mid50k_counters.md")
-TRI_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "k_tri_tiled.h", "k_launch.hip", "k_inst.hip",
+TRI_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "k_tri_tiled.h", "k_tri_code.h", "k_launch.hip", "k_inst.hip",
                "nw_api.cpp"]
 
 
@@ -509,7 +509,7 @@ def main():
         # algorithmic bytes of the main pass: the words read once (48-byte
         # slots) and every word's top-k list written once (int16 + int32)
         alg_bytes = dv.n * 48 + dv.n * k * 6
-        rec["roofline"] = roofline(cells, main_ms / 1e3, "k_topk_tiled (all-pairs main pass, every LA)",
+        rec["roofline"] = roofline(cells, main_ms / 1e3, "k_topk_code (all-pairs main pass, every LA)",
                                    None if tr is None else tr[0] + tr[1], alg_bytes)
         rate = measured_packed_peak(nw, torch)
         rec["roofline"]["measured_peak"] = {
@@ -540,7 +540,7 @@ def main():
                                      "+1/-1, gap -1)", "n_words": dv.n, "pairs": E, "cells": cells}
         tr = counter_traffic(TRI_COUNTER_SUMMARY, TRI_SOURCES) if args.workload == "mid" else None
         # algorithmic bytes: one int8 score written per pair, the words read once
-        rec["roofline"] = roofline(cells, ms_per_step / 1e3, "k_tri_tiled (every LA)",
+        rec["roofline"] = roofline(cells, ms_per_step / 1e3, "k_tri_code (every LA)",
                                    None if tr is None else tr[0] + tr[1], E + dv.n * 48)
         if tr is not None:
             # algorithmic bytes: one int8 score written per pair; the words read are ~1 MB

@@ -8,6 +8,8 @@
 #include "k_edges.h"
 #include "k_query.h"
 #include "k_topk.h"
+#include "k_topk_code.h"
+#include "k_tri_code.h"
 #include "k_tri_tiled.h"
 #include "nw_kernels.h"
 
@@ -20,8 +22,10 @@ template <int LO, int... Is>
 static void fill(KernelTables &t, std::integer_sequence<int, Is...>)
 {
     ((t.tri[LO + Is] = reinterpret_cast<const void *>(&k_tri_tiled<LO + Is>)), ...);
+    ((t.tri_code[LO + Is] = reinterpret_cast<const void *>(&k_tri_code<LO + Is>)), ...);
     ((t.query[LO + Is] = reinterpret_cast<const void *>(&k_query_tiled<LO + Is>)), ...);
     ((t.topk[LO + Is] = reinterpret_cast<const void *>(&k_topk_tiled<LO + Is>)), ...);
+    ((t.topk_code[LO + Is] = reinterpret_cast<const void *>(&k_topk_code<LO + Is>)), ...);
     ((t.edges[LO + Is] = reinterpret_cast<const void *>(&k_edges_tiled<LO + Is>)), ...);
     ((t.persist1[LO + Is] = reinterpret_cast<const void *>(&k_tri_persist<LO + Is, LO + Is>)), ...);
 }

@@ -6,12 +6,16 @@
 // row of the score matrix instead of the whole matrix).
 #define NW_LAUNCH_TU 1
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "k_batch.h"
 #include "k_diag.h"
 #include "k_edges.h"
 #include "k_query.h"
 #include "k_topk.h"
+#include "k_topk_code.h"
+#include "k_tri_code.h"
 #include "k_tri_tiled.h"
 #include "nw_fork.h"
 #include "nw_kernels.h"
@@ -141,6 +145,17 @@ static uint32_t tile_chunks(uint64_t tiles, uint32_t maxrp)
     return std::max<uint32_t>(1, std::min(want, maxrp / kMinRowPairs));
 }
 
+// NW_EPILOGUE=plain keeps the kernels with the plain integer epilogue where
+// the score-code kernels would apply (both are exact; for comparisons).
+static bool plain_epilogue_only()
+{
+    static const bool only = [] {
+        const char *e = std::getenv("NW_EPILOGUE");
+        return e && std::strcmp(e, "plain") == 0;
+    }();
+    return only;
+}
+
 hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uint64_t idx_begin, uint64_t idx_end,
                                  int out_kind, void *d_out, hipStream_t stream, const EdgeSink *E, StreamFork *shared)
 {
@@ -184,10 +199,23 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
         }
         return shared ? hipSuccess : own.end();
     }
+    const bool code_ok = out_kind != OUT_EDGES && !plain_epilogue_only();
     for (int LA = 0; LA <= V.lmax; ++LA) {
         if (h_maxrp[LA] == 0) continue;   // no block has row pairs of this length
         uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);
         uint32_t rpc = (h_maxrp[LA] + chunks - 1) / chunks;
+        int esz = out_kind == OUT_I8 ? 1 : 2;
+        if (code_ok && tri_code_applies(V, LA, esz)) {
+            DevVocab Vc = V;
+            uint64_t ib = idx_begin, ie = idx_end;
+            void *po = d_out;
+            uint32_t rb0 = G.rb0, rbn = G.rbn;
+            void *args[] = {&Vc, &ib, &ie, &po, &esz, &rb0, &rbn, &chunks, &rpc};
+            hipError_t e = launch_dyn(tab.tri_code[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
+                                      tri_code_lds_bytes(LA, V.alphabet, V.CB, esz), fork, args);
+            if (e != hipSuccess) return e;
+            continue;
+        }
         DevVocab Vc = V;
         uint64_t ib = idx_begin, ie = idx_end;
         void *po = d_out;
@@ -363,13 +391,22 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
     for (int LA = 0; LA <= V.lmax; ++LA) {
         DevVocab Vc = V;
         TopkArgs Tc = T;
-        // the histogram copies go to LDS when they fit beside the profiles
-        // (large alphabets with wide score ranges add to global bins instead)
-        Tc.hist_in_lds = T.hist != nullptr && T.nbins <= kLdsHistMax &&
-                         topk_lds_bytes(LA, V.alphabet, T.nbins, 1, V.CB) <= kMaxLdsBytes;
-        void *args[] = {&Vc, &Tc};
-        hipError_t e = launch_dyn(tab.topk[LA], dim3(nblk_pairs),
-                                  topk_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), fork, args);
+        hipError_t e;
+        if (!plain_epilogue_only() && topk_code_applies(V, T, LA)) {
+            // score codes within [0, 1024), the histogram in LDS below 64 KiB
+            Tc.hist_in_lds = T.hist != nullptr;
+            void *args[] = {&Vc, &Tc};
+            e = launch_dyn(tab.topk_code[LA], dim3(nblk_pairs),
+                           topk_code_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), fork, args);
+        } else {
+            // the histogram copies go to LDS when they fit beside the profiles
+            // (large alphabets with wide score ranges add to global bins instead)
+            Tc.hist_in_lds = T.hist != nullptr && T.nbins <= kLdsHistMax &&
+                             topk_lds_bytes(LA, V.alphabet, T.nbins, 1, V.CB) <= kMaxLdsBytes;
+            void *args[] = {&Vc, &Tc};
+            e = launch_dyn(tab.topk[LA], dim3(nblk_pairs), topk_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB),
+                           fork, args);
+        }
         if (e != hipSuccess) return e;
     }
     return fork.end();

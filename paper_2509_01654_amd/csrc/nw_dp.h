@@ -133,3 +133,20 @@ __device__ __forceinline__ h2 dp_lane(const uint32_t (&bw)[LBMAX / 4], int lbmax
 }
 
 }  // namespace nw
+
+namespace nw {
+
+// LDS byte addresses as plain integers: the address of a __shared__ object,
+// and typed pointers at an address.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+__device__ __forceinline__ uint32_t lds_addr_of(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)p;
+}
+__device__ __forceinline__ lds_u32 *lds_ptr(uint32_t addr) { return (lds_u32 *)(uintptr_t)addr; }
+__device__ __forceinline__ lds_u16 *lds_ptr16(uint32_t addr) { return (lds_u16 *)(uintptr_t)addr; }
+__device__ __forceinline__ lds_u8 *lds_ptr8(uint32_t addr) { return (lds_u8 *)(uintptr_t)addr; }
+
+}  // namespace nw

@@ -15,8 +15,10 @@ constexpr int kNumClass8 = 7;
 
 struct KernelTables {
     const void *tri[kMaxLen + 1];
+    const void *tri_code[kMaxLen + 1];   // the same with score codes and dword stores
     const void *query[kMaxLen + 1];
     const void *topk[kMaxLen + 1];
+    const void *topk_code[kMaxLen + 1];  // the same with the score-code epilogue
     const void *edges[kMaxLen + 1];      // threshold edge emitter
     const void *persist1[kMaxLen + 1];   // persistent batched kernel, one per row length
     const void *persist8[kNumClass8];    // persistent batched kernel, one per class of 8 lengths
