@@ -67,6 +67,42 @@ def test_paper_top32_histogram_sampled_rows(paper):
         np.testing.assert_array_equal(sc[r].astype(np.int32), ws[0], err_msg=f"row {r}")
 
 
+def _fixture_module():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_topk600k.py")
+    spec = importlib.util.spec_from_file_location("make_topk600k", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_paper_top32_every_row_against_fixture(paper):
+    """600,000 words, k = 32: every row's list and every histogram bin against
+    the oracle's run over all rows (stored as SHA-256 digests of 1,024-row
+    blocks, tests/golden/topk600k_paper.txt), the byte-for-byte comparison of
+    CPU and GPU outputs of Section 5."""
+    import os
+    fx = _fixture_module()
+    if not os.path.exists(fx.FIXTURE):
+        pytest.skip("the 600k oracle fixture has not been generated")
+    want = fx.read_fixture()
+    v, dv = paper
+    assert want["dataset_sha256"] == synth.sha256_vocab(v), "the fixture belongs to another dataset"
+    assert want["n"] == v.n and want["k"] == 32
+    _report("full size: 600k top-32 every row against the oracle fixture")
+    sc, ix, h = dv.all_pairs_topk(32)
+    torch.cuda.synchronize()
+    sc, ix, h = sc.cpu().numpy(), ix.cpu().numpy(), h.cpu().numpy().astype(np.uint64)
+    lo, _ = dv.bounds
+    assert lo == want["hist_lo"]
+    np.testing.assert_array_equal(h, want["hist"], err_msg="histogram bins differ from the oracle")
+    B = want["block_rows"]
+    bad = [blk for blk in range((v.n + B - 1) // B)
+           if fx.block_digest(sc[blk * B:(blk + 1) * B], ix[blk * B:(blk + 1) * B]) != want["blocks"][blk]]
+    assert not bad, f"{len(bad)} blocks of {B} rows differ from the oracle, first {bad[:8]}"
+
+
 def test_mid_triangle_sampled_pairs():
     """50,000 words, the int8 triangle of the bench: a random sample of 10^6 pair
     indices, every block-boundary row start, the last pairs, and two full blocks
