@@ -25,7 +25,7 @@ static void fill(KernelTables &t, std::integer_sequence<int, Is...>)
     ((t.tri_code[LO + Is] = reinterpret_cast<const void *>(&k_tri_code<LO + Is>)), ...);
     ((t.query[LO + Is] = reinterpret_cast<const void *>(&k_query_tiled<LO + Is>)), ...);
     ((t.topk[LO + Is] = reinterpret_cast<const void *>(&k_topk_tiled<LO + Is>)), ...);
-    ((t.topk_code[LO + Is] = reinterpret_cast<const void *>(&k_topk_code<LO + Is>)), ...);
+    ((t.topk_code[LO + Is] = reinterpret_cast<const void *>(&k_topk_code<LO + Is, topk_code_pairs(LO + Is)>)), ...);
     ((t.edges[LO + Is] = reinterpret_cast<const void *>(&k_edges_tiled<LO + Is>)), ...);
     ((t.persist1[LO + Is] = reinterpret_cast<const void *>(&k_tri_persist<LO + Is, LO + Is>)), ...);
 }

@@ -34,10 +34,19 @@ constexpr uint32_t kCodeOrigin = 0x6400u;
 constexpr uint32_t kCodeNever = 0x7FFFu;
 constexpr int kCodeMaxBins = 256;
 
+// Row pairs per step of k_topk_code<LA, R>: two for the short rows, whose
+// per-column address and per-column-word work weigh most; one where the two
+// DP columns would not fit beside the other registers.
+constexpr int kTopkPairMaxLA = 16;
+__host__ __device__ constexpr int topk_code_pairs(int LA) { return LA >= 1 && LA <= kTopkPairMaxLA ? 2 : 1; }
+__host__ __device__ constexpr uint32_t topk_code_profile_bytes(int LA, int R, int alphabet)
+{
+    return R == 2 ? profile2_bytes(LA, alphabet) : profile_bytes(LA, alphabet);
+}
 __host__ __device__ constexpr uint32_t topk_code_lds_bytes(int LA, int alphabet, int nbins, int has_hist, int CB)
 {
-    return 2u * profile_bytes(LA, alphabet) + topk_hist_bytes(nbins, has_hist) + 8u * (uint32_t)CB +
-           topk_pool_bytes();
+    return 2u * topk_code_profile_bytes(LA, topk_code_pairs(LA), alphabet) + topk_hist_bytes(nbins, has_hist) +
+           8u * (uint32_t)CB + topk_pool_bytes();
 }
 
 // Does the main pass of this dictionary with these arguments take
@@ -46,7 +55,8 @@ __host__ __device__ constexpr uint32_t topk_code_lds_bytes(int LA, int alphabet,
 __host__ __device__ inline bool topk_code_applies(const DevVocab &V, const TopkArgs &T, int LA)
 {
     return T.lo <= V.lo && V.hi - T.lo < 1024 && (T.hist == nullptr || T.nbins <= kCodeMaxBins) &&
-           2u * profile_bytes(LA, V.alphabet) + topk_hist_bytes(T.nbins, T.hist != nullptr) <= 65536u &&
+           2u * topk_code_profile_bytes(LA, topk_code_pairs(LA), V.alphabet) +
+                   topk_hist_bytes(T.nbins, T.hist != nullptr) <= 65536u &&
            topk_code_lds_bytes(LA, V.alphabet, T.nbins, T.hist != nullptr, V.CB) <= kMaxLdsBytes;
 }
 
@@ -57,7 +67,11 @@ __device__ __forceinline__ uint32_t threshold_code(int ts, int lo)
     return (uint32_t)min(max(c, 0), (int)kCodeNever);
 }
 
-template <int LA>
+// R row pairs per step (1 or 2): with two, the profile holds both pairs
+// (build_profile2) and one address per column serves both (dp_lane2), so
+// the per-column address, the per-column-word metadata, the barrier and the
+// column word loads are shared by twice the cells.
+template <int LA, int R>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(topk_min_waves<LA>())))
 void k_topk_code(DevVocab V, TopkArgs T)
 {
@@ -75,7 +89,7 @@ void k_topk_code(DevVocab V, TopkArgs T)
     const int64_t J0 = (int64_t)b * CB;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const uint32_t prof_bytes = profile_bytes(LA, V.alphabet);
+    const uint32_t prof_bytes = topk_code_profile_bytes(LA, R, V.alphabet);
     const bool has_hist = T.hist != nullptr;
     const uint32_t hs = hist_stride(T.nbins);
     const uint32_t lds0 = lds_addr_of(lds);
@@ -115,72 +129,110 @@ void k_topk_code(DevVocab V, TopkArgs T)
     const int CPL = V.CB / kThreads;
     const int lane_base = wave * 64 + lane;
 
-    for (uint32_t k = pbeg; k < pend; ++k) {
-        const int32_t a0 = V.rpairs[2 * k], a1 = V.rpairs[2 * k + 1];
-        const uint8_t *prof = lds + (k & 1) * prof_bytes;
-        build_profile<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (k & 1) * prof_bytes),
-                          V.bsym + (int64_t)a0 * kWordBytes, V.bsym + (int64_t)(a1 >= 0 ? a1 : a0) * kWordBytes, role);
+    for (uint32_t k = pbeg, it = 0; k < pend; k += R, ++it) {
+        // the row words of this step: halves h = 0, 1 (first pair), 2, 3 (second pair)
+        int32_t sl[2 * R];
+        sl[0] = V.rpairs[2 * k];
+        sl[1] = V.rpairs[2 * k + 1];
+        if constexpr (R == 2) {
+            const bool more = k + 1 < pend;
+            sl[2] = more ? V.rpairs[2 * k + 2] : -1;
+            sl[3] = more ? V.rpairs[2 * k + 3] : -1;
+        }
+        const uint8_t *prof = lds + (it & 1) * prof_bytes;
+        {
+            auto wp = [&](int h) { return V.bsym + (int64_t)(sl[h] >= 0 ? sl[h] : sl[0]) * kWordBytes; };
+            if constexpr (R == 1)
+                build_profile<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (it & 1) * prof_bytes),
+                                  wp(0), wp(1), role);
+            else
+                build_profile2<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (it & 1) * prof_bytes),
+                                   wp(0), wp(1), wp(2), wp(3), role);
+        }
         __syncthreads();
-        const int pb = (int)(k & 1);
+        const int pb = (int)(it & 1);
         {
             const uint32_t other = pool.n[pb ^ 1];
             if (other >= (uint32_t)kPoolFlush) pool_flush(pool, pb ^ 1, T, other);
         }
-        const int64_t u0 = I0 + V.bcol[a0];
-        const int64_t u1 = a1 >= 0 ? I0 + V.bcol[a1] : -1;
-        const uint32_t tu0 = threshold_code(key_score(T.thr[u0], T.lo), T.lo);
-        const uint32_t tu1 = u1 >= 0 ? threshold_code(key_score(T.thr[u1], T.lo), T.lo) : kCodeNever;
-        const u16x2 tu = u16x2{(uint16_t)tu0, (uint16_t)tu1};
-        // the short epilogue: every pair of the tile counts, both halves real
-        const bool fast = !diag && !padded && a1 >= 0;
+        int64_t u[2 * R];
+        uint32_t tu[2 * R];
+        bool all = true;
+#pragma unroll
+        for (int h = 0; h < 2 * R; ++h) {
+            u[h] = sl[h] >= 0 ? I0 + V.bcol[sl[h]] : -1;
+            tu[h] = u[h] >= 0 ? threshold_code(key_score(T.thr[u[h]], T.lo), T.lo) : kCodeNever;
+            all = all && sl[h] >= 0;
+        }
+        // the short epilogue: every pair of the tile counts, every half real
+        const bool fast = !diag && !padded && all;
 
         // the detailed tests of one pair whose code passed the combined test
-        auto offer = [&](uint32_t code, uint32_t tu_h, uint32_t tj, int64_t u, int64_t j) {
+        auto offer = [&](uint32_t code, uint32_t tu_h, uint32_t tj, int64_t uu, int64_t j) {
             const int s = (int)code - (int)kCodeOrigin + T.lo;
-            if (code >= tu_h) pool_offer(pool, pb, T, u, nb_key(s, T.lo, (uint32_t)j));
-            if (code >= tj) pool_offer(pool, pb, T, j, nb_key(s, T.lo, (uint32_t)u));
+            if (code >= tu_h) pool_offer(pool, pb, T, uu, nb_key(s, T.lo, (uint32_t)j));
+            if (code >= tj) pool_offer(pool, pb, T, j, nb_key(s, T.lo, (uint32_t)uu));
+        };
+        // general epilogue of one half: validity, histogram, thresholds
+        auto general = [&](uint32_t c, int h, uint32_t tj, int64_t j) {
+            // each unordered pair once: in a diagonal block only j > u
+            if (u[h] < 0 || (diag && j <= u[h])) return;
+            if (has_hist) atomicAdd(&hist[(int)c - (int)kCodeOrigin + T.lo], 1u);
+            if (c >= min(tu[h], tj)) offer(c, tu[h], tj, u[h], j);
         };
         auto column = [&](const uint32_t(&bw)[kWordBytes / 4], int c) __attribute__((always_inline)) {
             const uint2 m = meta[lane_base + c * kThreads];
             const int lbmax_w = (int)((uint32_t)__builtin_amdgcn_readlane((int)m.y, 63) >> 16);
-            h2 g;
-            if constexpr (LA == 0)
-                g = h2{0, 0};
-            else
-                g = dp_lane<LA, kWordBytes>(bw, lbmax_w, prof, profile_stride_dw<LA>() * 4u);
-            const uint32_t code = __builtin_bit_cast(uint32_t, g + as_h2(m.x).yy);
-            const u16x2 cv = __builtin_bit_cast(u16x2, code);
+            h2 g[R];
+            if constexpr (LA == 0) {
+                g[0] = h2{0, 0};
+            } else if constexpr (R == 1) {
+                g[0] = dp_lane<LA, kWordBytes>(bw, lbmax_w, prof, profile_stride_dw<LA>() * 4u);
+            } else {
+                dp_lane2<LA, kWordBytes, profile2_off_b(LA)>(bw, lbmax_w, prof, profile2_stride_dw(LA) * 4u, g[0],
+                                                            g[1]);
+            }
+            uint32_t code[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) code[q] = __builtin_bit_cast(uint32_t, g[q] + as_h2(m.x).yy);
             const uint32_t tj = m.y & 0xFFFFu;
             if (fast) {
                 if (has_hist) {
-                    const uint32_t ha = __builtin_bit_cast(uint32_t, cv * u16x2{4, 4} + u16x2{hb, hb});
-                    __atomic_fetch_add(lds_ptr(ha & 0xFFFFu), 1u, __ATOMIC_RELAXED);
-                    __atomic_fetch_add(lds_ptr(ha >> 16), 1u, __ATOMIC_RELAXED);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        const uint32_t ha = __builtin_bit_cast(
+                            uint32_t, __builtin_bit_cast(u16x2, code[q]) * u16x2{4, 4} + u16x2{hb, hb});
+                        __atomic_fetch_add(lds_ptr(ha & 0xFFFFu), 1u, __ATOMIC_RELAXED);
+                        __atomic_fetch_add(lds_ptr(ha >> 16), 1u, __ATOMIC_RELAXED);
+                    }
                 }
-                // either half at or above min(its row threshold, the column threshold)?
-                const u16x2 mn = __builtin_elementwise_min(tu, u16x2{(uint16_t)tj, (uint16_t)tj});
-                const uint32_t d =
-                    __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, cv) - __builtin_bit_cast(i16x2, mn));
-                if (__builtin_expect((d & 0x80008000u) != 0x80008000u, 0)) {
+                // any half at or above min(its row threshold, the column threshold)?
+                uint32_t all_neg = 0x80008000u;
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const u16x2 mn = __builtin_elementwise_min(u16x2{(uint16_t)tu[2 * q], (uint16_t)tu[2 * q + 1]},
+                                                               u16x2{(uint16_t)tj, (uint16_t)tj});
+                    all_neg &= __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, code[q]) -
+                                                                 __builtin_bit_cast(i16x2, mn));
+                }
+                if (__builtin_expect(all_neg != 0x80008000u, 0)) {
                     const int64_t j = J0 + (int64_t)(m.x & 0xFFFFu);
-                    offer(code & 0xFFFFu, tu0, tj, u0, j);
-                    offer(code >> 16, tu1, tj, u1, j);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        offer(code[q] & 0xFFFFu, tu[2 * q], tj, u[2 * q], j);
+                        offer(code[q] >> 16, tu[2 * q + 1], tj, u[2 * q + 1], j);
+                    }
                 }
                 return;
             }
             const uint32_t col = m.x & 0xFFFFu;
             if (col == 0xFFFF) return;
             const int64_t j = J0 + col;
-            const uint32_t c0 = code & 0xFFFFu, c1 = code >> 16;
-            // each unordered pair once: in a diagonal block only j > u
-            const bool v0 = !diag || j > u0;
-            const bool v1 = u1 >= 0 && (!diag || j > u1);
-            if (has_hist) {
-                if (v0) atomicAdd(&hist[(int)c0 - (int)kCodeOrigin + T.lo], 1u);
-                if (v1) atomicAdd(&hist[(int)c1 - (int)kCodeOrigin + T.lo], 1u);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                general(code[q] & 0xFFFFu, 2 * q, tj, j);
+                general(code[q] >> 16, 2 * q + 1, tj, j);
             }
-            if (v0 && c0 >= min(tu0, tj)) offer(c0, tu0, tj, u0, j);
-            if (v1 && c1 >= min(tu1, tj)) offer(c1, tu1, tj, u1, j);
         };
         const uint8_t *wbase = V.bsym + (J0 + lane_base) * kWordBytes;
         auto word_at = [&](int c) { return wbase + (int64_t)min(c, CPL - 1) * kThreads * kWordBytes; };

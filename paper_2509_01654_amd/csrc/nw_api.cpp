@@ -412,6 +412,14 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
         const uint64_t u1 = std::min<uint64_t>(u0 + L.CB, n);
         for (auto &v : by_len) v.clear();
         for (uint64_t u = u0; u < u1; ++u) by_len[clen[u]].push_back((int)(u - u0));
+        // within a length, words in lexicographic order (ties by caller index):
+        // neighbouring lanes then often hold the same symbol in a column, and
+        // lanes reading the same profile row share one LDS access
+        for (int l = 1; l <= LM; ++l)
+            std::sort(by_len[l].begin(), by_len[l].end(), [&](int a, int b) {
+                const int c = std::memcmp(csym + (u0 + a) * L.WB, csym + (u0 + b) * L.WB, (size_t)l);
+                return c != 0 ? c < 0 : a < b;
+            });
         // padding slots first (length 0, marked by column 0xFFFF), then real words by length
         uint64_t s = u0;
         for (uint64_t p = u1; p < u0 + L.CB; ++p, ++s) { blen[s] = 0; bcol[s] = 0xFFFF; borig[s] = -1; }

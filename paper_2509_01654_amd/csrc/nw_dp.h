@@ -55,12 +55,12 @@ __device__ __forceinline__ uint32_t sym_at(const uint32_t (&bw)[NW], int j)
     return __builtin_amdgcn_ubfe(bw[j >> 2], (j & 3) * 8, 8);
 }
 
-template <int NQ>
+// The NQ 16-byte units of a profile row, QS bytes apart.
+template <int NQ, int QS = 16>
 __device__ __forceinline__ void load_row(u32x4 (&dst)[NQ], const uint8_t *row)
 {
-    const u32x4 *p = reinterpret_cast<const u32x4 *>(row);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) dst[q] = p[q];
+    for (int q = 0; q < NQ; ++q) dst[q] = *reinterpret_cast<const u32x4 *>(row + q * QS);
 }
 
 // Run the DP of two row words (profile `prof`, LA symbols each) against the
@@ -95,7 +95,7 @@ __device__ __forceinline__ void static_for(F &&f)
 // word and ends with G[LA][its own length], with no per-lane branch inside
 // the column sequence; the compiler then rotates the registers of col[]
 // freely instead of moving values back every column.
-template <int LA, int LBMAX>
+template <int LA, int LBMAX, int QS = 16>
 __device__ __forceinline__ h2 dp_lane(const uint32_t (&bw)[LBMAX / 4], int lbmax_w, const uint8_t *prof,
                                       uint32_t stride_b)
 {
@@ -105,7 +105,7 @@ __device__ __forceinline__ h2 dp_lane(const uint32_t (&bw)[LBMAX / 4], int lbmax
     for (int i = 0; i < LA; ++i) col[i] = h2{0, 0};
 
     u32x4 wa[NQ], wb[NQ];
-    load_row(wa, prof + sym_at(bw, 0) * stride_b);
+    load_row<NQ, QS>(wa, prof + sym_at(bw, 0) * stride_b);
     static_for<0, LBMAX>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j >= lbmax_w) return false;
@@ -113,10 +113,21 @@ __device__ __forceinline__ h2 dp_lane(const uint32_t (&bw)[LBMAX / 4], int lbmax
         u32x4(&nxt)[NQ] = (j & 1) ? wa : wb;
         // prefetch the profile row of the next column (past the end of a word
         // the bytes are the sentinel, a valid row, so the read is in bounds)
-        if constexpr (j + 1 < LBMAX) load_row(nxt, prof + sym_at(bw, j + 1) * stride_b);
+        if constexpr (j + 1 < LBMAX) load_row<NQ, QS>(nxt, prof + sym_at(bw, j + 1) * stride_b);
         // column j+1 of G: cell i+1 = max3(G[i][j] + w, G[i+1][j], G[i][j+1])
         h2 t = as_h2(cur[0][0]);   // G[0][j] = 0, plus w of row 0
         h2 up = h2{0, 0};          // G[0][j+1] = 0
+        if constexpr (j == 0) {
+            // the first column: G[i][0] = 0, so the diagonal candidates are
+            // the weights themselves and the left ones are 0
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                const h2 v = max3(as_h2(cur[i >> 2][i & 3]), h2{0, 0}, up);
+                col[i] = v;
+                up = v;
+            }
+            return true;
+        }
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             // the diagonal candidate of the next cell uses the old col[i]
@@ -130,6 +141,56 @@ __device__ __forceinline__ h2 dp_lane(const uint32_t (&bw)[LBMAX / 4], int lbmax
         return true;
     });
     return col[LA - 1];
+}
+
+// The DP of two row pairs at once: (u, u') from the profile half at prof and
+// (v, v') from the half at prof + off_b, both against the lane's word.  Row c
+// of the two-pair profile holds both halves, so one address per column serves
+// both pairs' reads (the second through the instruction's offset field).
+// Returns G[LA][len] of the first pair in ga, of the second in gb.
+template <int LA, int LBMAX, uint32_t OFF_B>
+__device__ __forceinline__ void dp_lane2(const uint32_t (&bw)[LBMAX / 4], int lbmax_w, const uint8_t *prof,
+                                         uint32_t stride_b, h2 &ga, h2 &gb)
+{
+    constexpr int NQ = (LA + 3) / 4;
+    h2 ca[LA], cb[LA];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) ca[i] = cb[i] = h2{0, 0};
+
+    u32x4 wa[NQ], wb[NQ];
+    static_for<0, LBMAX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j >= lbmax_w) return false;
+        const uint8_t *row = prof + sym_at(bw, j) * stride_b;
+        load_row(wa, row);
+        load_row(wb, row + OFF_B);
+        if constexpr (j == 0) {
+            h2 ua = h2{0, 0}, ub = h2{0, 0};
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                ca[i] = ua = max3(as_h2(wa[i >> 2][i & 3]), h2{0, 0}, ua);
+                cb[i] = ub = max3(as_h2(wb[i >> 2][i & 3]), h2{0, 0}, ub);
+            }
+            return true;
+        }
+        h2 ta = as_h2(wa[0][0]), tb = as_h2(wb[0][0]);
+        h2 ua = h2{0, 0}, ub = h2{0, 0};
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            h2 tna = h2{0, 0}, tnb = h2{0, 0};
+            if (i + 1 < LA) {
+                tna = ca[i] + as_h2(wa[(i + 1) >> 2][(i + 1) & 3]);
+                tnb = cb[i] + as_h2(wb[(i + 1) >> 2][(i + 1) & 3]);
+            }
+            ca[i] = ua = max3(ta, ca[i], ua);
+            cb[i] = ub = max3(tb, cb[i], ub);
+            ta = tna;
+            tb = tnb;
+        }
+        return true;
+    });
+    ga = ca[LA - 1];
+    gb = cb[LA - 1];
 }
 
 }  // namespace nw

@@ -29,7 +29,8 @@ constexpr uint32_t kSentinelPair = 0xE800E800u;
 //
 // Caller order: word u has length clen[u] and symbols csym[u*WB .. u*WB+len).
 // Blocked order: the words are cut into blocks of CB consecutive caller-order
-// words; inside each block they are sorted by length (stable).  Sorted slot
+// words; inside each block they are sorted by length, and words of one
+// length lexicographically (ties by caller index).  Sorted slot
 // s (global: block*CB + local) holds the word whose caller index is
 // block*CB + bcol[s]; its symbols are bsym[s*WB ..] and its length blen[s]
 // (0 for the padding slots of the last block).

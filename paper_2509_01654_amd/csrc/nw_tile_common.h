@@ -102,6 +102,39 @@ __device__ __forceinline__ void build_profile(const uint16_t *wtab, int A, uint3
     }
 }
 
+// Two-pair profile: row c holds the first pair's LA dwords (padded to whole
+// 16-byte units), then the second pair's, then one spare unit, so rows are an
+// odd number of 16-byte units apart as in the one-pair layout.
+__host__ __device__ constexpr uint32_t profile2_stride_dw(int LA) { return (uint32_t)(((LA + 3) / 4) * 8 + 4); }
+__host__ __device__ constexpr uint32_t profile2_off_b(int LA) { return (uint32_t)((LA + 3) / 4) * 16u; }
+__host__ __device__ constexpr uint32_t profile2_bytes(int LA, int alphabet)
+{
+    return LA == 0 ? 0u : (uint32_t)(alphabet + 1) * profile2_stride_dw(LA) * 4u;
+}
+
+// Build the two-pair profile of row pairs (su, su2) and (sv, sv2).
+template <int LA>
+__device__ __forceinline__ void build_profile2(const uint16_t *wtab, int A, uint32_t *prof, const uint8_t *su,
+                                               const uint8_t *su2, const uint8_t *sv, const uint8_t *sv2,
+                                               const ProfileRole &role)
+{
+    constexpr uint32_t S = profile2_stride_dw(LA);
+    constexpr uint32_t OB = profile2_off_b(LA) / 4;
+    const int c = role.c;
+    if (c < 0) return;
+    if (c == A) {
+        for (int i = role.i0; i < 2 * LA; i += role.G) prof[c * S + (i < LA ? i : OB + i - LA)] = kSentinelPair;
+        return;
+    }
+    for (int i = role.i0; i < 2 * LA; i += role.G) {
+        const bool second = i >= LA;
+        const int p = second ? i - LA : i;
+        const uint32_t lo = wtab[(int)(second ? sv : su)[p] * A + c];
+        const uint32_t hi = wtab[(int)(second ? sv2 : su2)[p] * A + c];
+        prof[c * S + (second ? OB + p : p)] = lo | (hi << 16);
+    }
+}
+
 // The symbols of a padded word as 32-bit registers.
 __device__ __forceinline__ void load_word(uint32_t (&bw)[kWordBytes / 4], const uint8_t *p)
 {

@@ -94,9 +94,12 @@ def test_paper_top32_every_row_against_fixture(paper):
     sc, ix, h = dv.all_pairs_topk(32)
     torch.cuda.synchronize()
     sc, ix, h = sc.cpu().numpy(), ix.cpu().numpy(), h.cpu().numpy().astype(np.uint64)
-    lo, _ = dv.bounds
-    assert lo == want["hist_lo"]
-    np.testing.assert_array_equal(h, want["hist"], err_msg="histogram bins differ from the oracle")
+    # the fixture's bins cover -32 .. 32; the dictionary's own score range lies inside
+    lo, hi = dv.bounds
+    a, b = lo - want["hist_lo"], hi - want["hist_lo"] + 1
+    assert 0 <= a and b <= len(want["hist"]) and len(h) == b - a
+    np.testing.assert_array_equal(h, want["hist"][a:b], err_msg="histogram bins differ from the oracle")
+    assert not want["hist"][:a].any() and not want["hist"][b:].any()
     B = want["block_rows"]
     bad = [blk for blk in range((v.n + B - 1) // B)
            if fx.block_digest(sc[blk * B:(blk + 1) * B], ix[blk * B:(blk + 1) * B]) != want["blocks"][blk]]
