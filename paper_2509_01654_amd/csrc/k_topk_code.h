@@ -43,18 +43,39 @@ __host__ __device__ constexpr uint32_t topk_code_profile_bytes(int LA, int R, in
 {
     return R == 2 ? profile2_bytes(LA, alphabet) : profile_bytes(LA, alphabet);
 }
+// Row pairs staged in LDS at a time (their words' symbols, caller indices and
+// threshold codes), so the per-step profile build and threshold reads wait on
+// LDS only; the staging itself costs one more barrier per chunk.
+constexpr int kChunkPairs = 32;
+__host__ __device__ constexpr uint32_t chunk_sym_bytes(int LA) { return (uint32_t)((LA + 3) / 4) * 4u; }
+__host__ __device__ constexpr uint32_t chunk_bytes(int LA)
+{
+    return 2u * kChunkPairs * (chunk_sym_bytes(LA) + 8u);
+}
+// The similarity table w(x, y) staged in LDS: alphabets up to 64 symbols.
+constexpr int kLdsWtabMaxAlphabet = 64;
+__host__ __device__ constexpr uint32_t wtab_lds_bytes(int alphabet)
+{
+    return ((uint32_t)alphabet * (uint32_t)alphabet * 2u + 15u) & ~15u;
+}
+// LDS of k_topk_code: two profile buffers, the histogram copies, 4 bytes of
+// metadata per column slot, the longest length of each group of 64 slots, the
+// similarity table, two row-pair chunks and the candidate pools.
 __host__ __device__ constexpr uint32_t topk_code_lds_bytes(int LA, int alphabet, int nbins, int has_hist, int CB)
 {
     return 2u * topk_code_profile_bytes(LA, topk_code_pairs(LA), alphabet) + topk_hist_bytes(nbins, has_hist) +
-           8u * (uint32_t)CB + topk_pool_bytes();
+           4u * (uint32_t)CB + (((uint32_t)CB / 64u + 15u) & ~15u) + wtab_lds_bytes(alphabet) +
+           2u * chunk_bytes(LA) + topk_pool_bytes();
 }
 
 // Does the main pass of this dictionary with these arguments take
-// k_topk_code<LA>?  Every score code lies in [0, 1024), and the histogram
-// copies (placed after the two profiles) end below 64 KiB.
+// k_topk_code<LA>?  Every score code lies in [0, 1024), the alphabet's table
+// fits in LDS, and the histogram copies (placed after the two profiles) end
+// below 64 KiB.
 __host__ __device__ inline bool topk_code_applies(const DevVocab &V, const TopkArgs &T, int LA)
 {
     return T.lo <= V.lo && V.hi - T.lo < 1024 && (T.hist == nullptr || T.nbins <= kCodeMaxBins) &&
+           V.alphabet <= kLdsWtabMaxAlphabet &&
            2u * topk_code_profile_bytes(LA, topk_code_pairs(LA), V.alphabet) +
                    topk_hist_bytes(T.nbins, T.hist != nullptr) <= 65536u &&
            topk_code_lds_bytes(LA, V.alphabet, T.nbins, T.hist != nullptr, V.CB) <= kMaxLdsBytes;
@@ -71,8 +92,18 @@ __device__ __forceinline__ uint32_t threshold_code(int ts, int lo)
 // (build_profile2) and one address per column serves both (dp_lane2), so
 // the per-column address, the per-column-word metadata, the barrier and the
 // column word loads are shared by twice the cells.
+// Waves per SIMD the compiler is asked to fit in registers: as many as the
+// LDS of the 40-symbol workload admits (six workgroups per CU up to LA = 8
+// with two pairs per step, five up to 12); longer rows keep the compiler's
+// own allocation.
 template <int LA, int R>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(topk_min_waves<LA>())))
+constexpr int topk_code_min_waves()
+{
+    return R == 1 ? topk_min_waves<LA>() : LA <= 8 ? 6 : LA <= 12 ? 5 : 1;
+}
+
+template <int LA, int R>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(topk_code_min_waves<LA, R>())))
 void k_topk_code(DevVocab V, TopkArgs T)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -87,9 +118,10 @@ void k_topk_code(DevVocab V, TopkArgs T)
     const int64_t n = V.n, CB = V.CB;
     const int64_t I0 = (int64_t)r * CB;
     const int64_t J0 = (int64_t)b * CB;
+    const int A = V.alphabet;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const uint32_t prof_bytes = topk_code_profile_bytes(LA, R, V.alphabet);
+    const uint32_t prof_bytes = topk_code_profile_bytes(LA, R, A);
     const bool has_hist = T.hist != nullptr;
     const uint32_t hs = hist_stride(T.nbins);
     const uint32_t lds0 = lds_addr_of(lds);
@@ -102,13 +134,17 @@ void k_topk_code(DevVocab V, TopkArgs T)
     const uint16_t hb = (uint16_t)(lds0 + my_hist - kCodeOrigin * 4u);
     if (has_hist)
         for (int i = tid; i < kHistCopies * (int)hs; i += kThreads) hist_all[i] = 0;
-    // column metadata: x = column | K << 16 (K = binary16 of 1024 - lo + gap (LA + lb)),
-    // y = threshold code of the column word | lb << 16
+    // per column slot: K | threshold code << 16 (K = binary16 of 1024 - lo + gap (LA + lb));
+    // per group of 64 slots: the longest length (the last slot's: slots are length-sorted)
     const uint32_t meta_off = hist_off + topk_hist_bytes(T.nbins, has_hist);
-    uint2 *meta = reinterpret_cast<uint2 *>(lds + meta_off);
+    uint32_t *meta = reinterpret_cast<uint32_t *>(lds + meta_off);
+    uint8_t *gmax = lds + meta_off + 4u * (uint32_t)CB;
+    uint16_t *wt = reinterpret_cast<uint16_t *>(gmax + (((uint32_t)CB / 64u + 15u) & ~15u));
+    uint8_t *chunks = reinterpret_cast<uint8_t *>(wt) + wtab_lds_bytes(A);
+    constexpr uint32_t SW = chunk_sym_bytes(LA);
     CandPool pool;
     {
-        uint8_t *pb = lds + meta_off + 8u * (uint32_t)CB;
+        uint8_t *pb = chunks + 2u * chunk_bytes(LA);
         pool.key = reinterpret_cast<uint64_t *>(pb);
         pool.word = reinterpret_cast<int32_t *>(pb + 2 * kPool * 8);
         pool.n = reinterpret_cast<uint32_t *>(pb + 2 * kPool * 12);
@@ -121,33 +157,46 @@ void k_topk_code(DevVocab V, TopkArgs T)
         const _Float16 kf = (_Float16)(float)(1024 - T.lo + V.gap * (LA + (int)lb));
         const uint32_t kbits = __builtin_bit_cast(uint16_t, kf);
         const uint32_t tj = col != 0xFFFF ? threshold_code(key_score(T.thr[J0 + col], T.lo), T.lo) : kCodeNever;
-        meta[i] = make_uint2(col | (kbits << 16), tj | (lb << 16));
+        meta[i] = kbits | (tj << 16);
+        if ((i & 63) == 63) gmax[i >> 6] = (uint8_t)lb;
     }
+    for (int i = tid; i < A * A; i += kThreads) wt[i] = V.wtab[i];
     const bool diag = r == b;
     const bool padded = (int64_t)(b + 1) * CB > n;   // the last block holds padding slots
-    const ProfileRole role = profile_role(tid, V.alphabet);
+    const ProfileRole role = profile_role(tid, A);
     const int CPL = V.CB / kThreads;
     const int lane_base = wave * 64 + lane;
 
     for (uint32_t k = pbeg, it = 0; k < pend; k += R, ++it) {
-        // the row words of this step: halves h = 0, 1 (first pair), 2, 3 (second pair)
-        int32_t sl[2 * R];
-        sl[0] = V.rpairs[2 * k];
-        sl[1] = V.rpairs[2 * k + 1];
-        if constexpr (R == 2) {
-            const bool more = k + 1 < pend;
-            sl[2] = more ? V.rpairs[2 * k + 2] : -1;
-            sl[3] = more ? V.rpairs[2 * k + 3] : -1;
+        // row-pair chunk: words' symbols, caller indices and threshold codes
+        const uint32_t kc = (k - pbeg) % kChunkPairs;
+        uint8_t *chunk = chunks + ((k - pbeg) / kChunkPairs & 1) * chunk_bytes(LA);
+        uint8_t *csym = chunk;
+        int32_t *cu = reinterpret_cast<int32_t *>(chunk + 2 * kChunkPairs * SW);
+        uint32_t *ctu = reinterpret_cast<uint32_t *>(cu + 2 * kChunkPairs);
+        if (kc == 0) {
+            if (tid < 2 * kChunkPairs) {
+                const uint32_t kk = k + (uint32_t)(tid >> 1);
+                const int32_t slot = kk < pend ? V.rpairs[2 * kk + (tid & 1)] : -1;
+                const int64_t uu = slot >= 0 ? I0 + V.bcol[slot] : -1;
+                cu[tid] = (int32_t)uu;
+                ctu[tid] = uu >= 0 ? threshold_code(key_score(T.thr[uu], T.lo), T.lo) : kCodeNever;
+                // an absent word takes symbol 0 throughout: any valid profile, never counted
+                const uint32_t *src = reinterpret_cast<const uint32_t *>(V.bsym + (int64_t)(slot >= 0 ? slot : 0) * kWordBytes);
+#pragma unroll
+                for (uint32_t q = 0; q < SW / 4; ++q)
+                    reinterpret_cast<uint32_t *>(csym + tid * SW)[q] = slot >= 0 ? src[q] : 0u;
+            }
+            __syncthreads();
         }
         const uint8_t *prof = lds + (it & 1) * prof_bytes;
         {
-            auto wp = [&](int h) { return V.bsym + (int64_t)(sl[h] >= 0 ? sl[h] : sl[0]) * kWordBytes; };
+            auto wp = [&](int h) { return csym + (2 * kc + h) * SW; };
             if constexpr (R == 1)
-                build_profile<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (it & 1) * prof_bytes),
-                                  wp(0), wp(1), role);
+                build_profile<LA>(wt, A, reinterpret_cast<uint32_t *>(lds + (it & 1) * prof_bytes), wp(0), wp(1), role);
             else
-                build_profile2<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (it & 1) * prof_bytes),
-                                   wp(0), wp(1), wp(2), wp(3), role);
+                build_profile2<LA>(wt, A, reinterpret_cast<uint32_t *>(lds + (it & 1) * prof_bytes), wp(0), wp(1),
+                                   wp(2), wp(3), role);
         }
         __syncthreads();
         const int pb = (int)(it & 1);
@@ -160,15 +209,16 @@ void k_topk_code(DevVocab V, TopkArgs T)
         bool all = true;
 #pragma unroll
         for (int h = 0; h < 2 * R; ++h) {
-            u[h] = sl[h] >= 0 ? I0 + V.bcol[sl[h]] : -1;
-            tu[h] = u[h] >= 0 ? threshold_code(key_score(T.thr[u[h]], T.lo), T.lo) : kCodeNever;
-            all = all && sl[h] >= 0;
+            u[h] = cu[2 * kc + h];
+            tu[h] = ctu[2 * kc + h];
+            all = all && u[h] >= 0;
         }
         // the short epilogue: every pair of the tile counts, every half real
         const bool fast = !diag && !padded && all;
 
         // the detailed tests of one pair whose code passed the combined test
         auto offer = [&](uint32_t code, uint32_t tu_h, uint32_t tj, int64_t uu, int64_t j) {
+            if (uu < 0) return;
             const int s = (int)code - (int)kCodeOrigin + T.lo;
             if (code >= tu_h) pool_offer(pool, pb, T, uu, nb_key(s, T.lo, (uint32_t)j));
             if (code >= tj) pool_offer(pool, pb, T, j, nb_key(s, T.lo, (uint32_t)uu));
@@ -181,8 +231,9 @@ void k_topk_code(DevVocab V, TopkArgs T)
             if (c >= min(tu[h], tj)) offer(c, tu[h], tj, u[h], j);
         };
         auto column = [&](const uint32_t(&bw)[kWordBytes / 4], int c) __attribute__((always_inline)) {
-            const uint2 m = meta[lane_base + c * kThreads];
-            const int lbmax_w = (int)((uint32_t)__builtin_amdgcn_readlane((int)m.y, 63) >> 16);
+            const int sl = lane_base + c * kThreads;   // local column slot
+            const uint32_t mt = meta[sl];
+            const int lbmax_w = __builtin_amdgcn_readfirstlane((int)gmax[sl >> 6]);
             h2 g[R];
             if constexpr (LA == 0) {
                 g[0] = h2{0, 0};
@@ -194,8 +245,8 @@ void k_topk_code(DevVocab V, TopkArgs T)
             }
             uint32_t code[R];
 #pragma unroll
-            for (int q = 0; q < R; ++q) code[q] = __builtin_bit_cast(uint32_t, g[q] + as_h2(m.x).yy);
-            const uint32_t tj = m.y & 0xFFFFu;
+            for (int q = 0; q < R; ++q) code[q] = __builtin_bit_cast(uint32_t, g[q] + as_h2(mt).xx);
+            const uint32_t tj = mt >> 16;
             if (fast) {
                 if (has_hist) {
 #pragma unroll
@@ -216,7 +267,7 @@ void k_topk_code(DevVocab V, TopkArgs T)
                                                                  __builtin_bit_cast(i16x2, mn));
                 }
                 if (__builtin_expect(all_neg != 0x80008000u, 0)) {
-                    const int64_t j = J0 + (int64_t)(m.x & 0xFFFFu);
+                    const int64_t j = J0 + (int64_t)V.bcol[J0 + sl];
 #pragma unroll
                     for (int q = 0; q < R; ++q) {
                         offer(code[q] & 0xFFFFu, tu[2 * q], tj, u[2 * q], j);
@@ -225,7 +276,7 @@ void k_topk_code(DevVocab V, TopkArgs T)
                 }
                 return;
             }
-            const uint32_t col = m.x & 0xFFFFu;
+            const uint32_t col = V.bcol[J0 + sl];
             if (col == 0xFFFF) return;
             const int64_t j = J0 + col;
 #pragma unroll
