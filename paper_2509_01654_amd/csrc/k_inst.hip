@@ -18,11 +18,21 @@
 
 namespace nw {
 
+template <int LA>
+static const void *tri_code2_kernel()
+{
+    if constexpr (LA >= 1 && LA <= kTopkPairMaxLA)
+        return reinterpret_cast<const void *>(&k_tri_code<LA, 2>);
+    else
+        return nullptr;
+}
+
 template <int LO, int... Is>
 static void fill(KernelTables &t, std::integer_sequence<int, Is...>)
 {
     ((t.tri[LO + Is] = reinterpret_cast<const void *>(&k_tri_tiled<LO + Is>)), ...);
-    ((t.tri_code[LO + Is] = reinterpret_cast<const void *>(&k_tri_code<LO + Is>)), ...);
+    ((t.tri_code1[LO + Is] = reinterpret_cast<const void *>(&k_tri_code<LO + Is, 1>)), ...);
+    ((t.tri_code2[LO + Is] = tri_code2_kernel<LO + Is>()), ...);
     ((t.query[LO + Is] = reinterpret_cast<const void *>(&k_query_tiled<LO + Is>)), ...);
     ((t.topk[LO + Is] = reinterpret_cast<const void *>(&k_topk_tiled<LO + Is>)), ...);
     ((t.topk_code[LO + Is] = reinterpret_cast<const void *>(&k_topk_code<LO + Is, topk_code_pairs(LO + Is)>)), ...);

@@ -205,14 +205,20 @@ hipError_t launch_triangle_tiled(const DevVocab &V, const uint32_t *h_maxrp, uin
         uint32_t chunks = tile_chunks(G.blocks, h_maxrp[LA]);
         uint32_t rpc = (h_maxrp[LA] + chunks - 1) / chunks;
         int esz = out_kind == OUT_I8 ? 1 : 2;
-        if (code_ok && tri_code_applies(V, LA, esz)) {
+        const int R = code_ok && tab.tri_code2[LA] && tri_code_applies(V, LA, esz, 2)   ? 2
+                      : code_ok && tri_code_applies(V, LA, esz, 1) ? 1
+                                                                   : 0;
+        if (R) {
+            // runs of whole steps
+            rpc = (rpc + R - 1) / R * R;
             DevVocab Vc = V;
             uint64_t ib = idx_begin, ie = idx_end;
             void *po = d_out;
             uint32_t rb0 = G.rb0, rbn = G.rbn;
             void *args[] = {&Vc, &ib, &ie, &po, &esz, &rb0, &rbn, &chunks, &rpc};
-            hipError_t e = launch_dyn(tab.tri_code[LA], dim3((uint32_t)((uint64_t)G.blocks * chunks)),
-                                      tri_code_lds_bytes(LA, V.alphabet, V.CB, esz), fork, args);
+            hipError_t e = launch_dyn(R == 2 ? tab.tri_code2[LA] : tab.tri_code1[LA],
+                                      dim3((uint32_t)((uint64_t)G.blocks * chunks)),
+                                      tri_code_lds_bytes(LA, V.alphabet, V.CB, esz, R), fork, args);
             if (e != hipSuccess) return e;
             continue;
         }

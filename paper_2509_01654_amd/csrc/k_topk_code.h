@@ -52,11 +52,13 @@ __host__ __device__ constexpr uint32_t chunk_bytes(int LA)
 {
     return 2u * kChunkPairs * (chunk_sym_bytes(LA) + 8u);
 }
-// The similarity table w(x, y) staged in LDS: alphabets up to 64 symbols.
-constexpr int kLdsWtabMaxAlphabet = 64;
+// The similarity table w(x, y) is staged in LDS for alphabets up to 48
+// symbols (4.5 KiB); larger tables are read from global memory, where they
+// stay cached, so that they do not cost workgroups per CU.
+constexpr int kLdsWtabMaxAlphabet = 48;
 __host__ __device__ constexpr uint32_t wtab_lds_bytes(int alphabet)
 {
-    return ((uint32_t)alphabet * (uint32_t)alphabet * 2u + 15u) & ~15u;
+    return alphabet <= kLdsWtabMaxAlphabet ? (((uint32_t)alphabet * (uint32_t)alphabet * 2u + 15u) & ~15u) : 0u;
 }
 // LDS of k_topk_code: two profile buffers, the histogram copies, 4 bytes of
 // metadata per column slot, the longest length of each group of 64 slots, the
@@ -69,13 +71,11 @@ __host__ __device__ constexpr uint32_t topk_code_lds_bytes(int LA, int alphabet,
 }
 
 // Does the main pass of this dictionary with these arguments take
-// k_topk_code<LA>?  Every score code lies in [0, 1024), the alphabet's table
-// fits in LDS, and the histogram copies (placed after the two profiles) end
-// below 64 KiB.
+// k_topk_code<LA>?  Every score code lies in [0, 1024), and the histogram
+// copies (placed after the two profiles) end below 64 KiB.
 __host__ __device__ inline bool topk_code_applies(const DevVocab &V, const TopkArgs &T, int LA)
 {
     return T.lo <= V.lo && V.hi - T.lo < 1024 && (T.hist == nullptr || T.nbins <= kCodeMaxBins) &&
-           V.alphabet <= kLdsWtabMaxAlphabet &&
            2u * topk_code_profile_bytes(LA, topk_code_pairs(LA), V.alphabet) +
                    topk_hist_bytes(T.nbins, T.hist != nullptr) <= 65536u &&
            topk_code_lds_bytes(LA, V.alphabet, T.nbins, T.hist != nullptr, V.CB) <= kMaxLdsBytes;
@@ -139,8 +139,8 @@ void k_topk_code(DevVocab V, TopkArgs T)
     const uint32_t meta_off = hist_off + topk_hist_bytes(T.nbins, has_hist);
     uint32_t *meta = reinterpret_cast<uint32_t *>(lds + meta_off);
     uint8_t *gmax = lds + meta_off + 4u * (uint32_t)CB;
-    uint16_t *wt = reinterpret_cast<uint16_t *>(gmax + (((uint32_t)CB / 64u + 15u) & ~15u));
-    uint8_t *chunks = reinterpret_cast<uint8_t *>(wt) + wtab_lds_bytes(A);
+    uint16_t *wt_lds = reinterpret_cast<uint16_t *>(gmax + (((uint32_t)CB / 64u + 15u) & ~15u));
+    uint8_t *chunks = reinterpret_cast<uint8_t *>(wt_lds) + wtab_lds_bytes(A);
     constexpr uint32_t SW = chunk_sym_bytes(LA);
     CandPool pool;
     {
@@ -160,7 +160,10 @@ void k_topk_code(DevVocab V, TopkArgs T)
         meta[i] = kbits | (tj << 16);
         if ((i & 63) == 63) gmax[i >> 6] = (uint8_t)lb;
     }
-    for (int i = tid; i < A * A; i += kThreads) wt[i] = V.wtab[i];
+    const bool wt_staged = A <= kLdsWtabMaxAlphabet;
+    if (wt_staged)
+        for (int i = tid; i < A * A; i += kThreads) wt_lds[i] = V.wtab[i];
+    const uint16_t *wt = wt_staged ? wt_lds : V.wtab;
     const bool diag = r == b;
     const bool padded = (int64_t)(b + 1) * CB > n;   // the last block holds padding slots
     const ProfileRole role = profile_role(tid, A);

@@ -37,18 +37,27 @@ constexpr uint32_t kTriCodeOrigin = 0x6500u;
 // Bytes of one staged row: CB scores, the spare slot, and slack for the
 // second dword a segment's last aligned read touches.
 __host__ __device__ constexpr uint32_t tri_code_stage_row(int CB, int es) { return (uint32_t)(CB + 8) * (uint32_t)es; }
-// Dynamic LDS: two profile buffers, the column metadata (8 bytes per slot) and
-// three staged row pairs.
-__host__ __device__ constexpr uint32_t tri_code_lds_bytes(int LA, int alphabet, int CB, int es)
+// Row pairs per step: two for the short rows (one column address serves
+// both, and the barrier and column loads are shared) while the buffers leave
+// at least four workgroups per CU; one otherwise.
+constexpr uint32_t kTriPairLdsBudget = 40u * 1024u;
+// Dynamic LDS: two profile buffers, 4 bytes of metadata per column slot, the
+// longest length of each group of 64 slots, the similarity table, two
+// row-pair chunks (symbols and caller indices) and three staged steps of
+// 2R rows each.
+__host__ __device__ constexpr uint32_t tri_chunk_bytes(int LA) { return 2u * kChunkPairs * (chunk_sym_bytes(LA) + 4u); }
+__host__ __device__ constexpr uint32_t tri_code_lds_bytes(int LA, int alphabet, int CB, int es, int R)
 {
-    return 2u * profile_bytes(LA, alphabet) + 8u * (uint32_t)CB + 6u * tri_code_stage_row(CB, es);
+    return 2u * topk_code_profile_bytes(LA, R, alphabet) + 4u * (uint32_t)CB + (((uint32_t)CB / 64u + 15u) & ~15u) +
+           wtab_lds_bytes(alphabet) + 2u * tri_chunk_bytes(LA) + 3u * 2u * (uint32_t)R * tri_code_stage_row(CB, es);
 }
 
-// Does a triangle call on this dictionary take k_tri_code<LA>?  Every score
-// lies in [-256, 768) and the buffers fit in LDS.
-__host__ __device__ inline bool tri_code_applies(const DevVocab &V, int LA, int es)
+// Does a triangle call on this dictionary take k_tri_code<LA, R>?  Every
+// score lies in [-256, 768) and the buffers fit.
+__host__ __device__ inline bool tri_code_applies(const DevVocab &V, int LA, int es, int R)
 {
-    return V.lo >= -256 && V.hi < 768 && tri_code_lds_bytes(LA, V.alphabet, V.CB, es) <= kMaxLdsBytes;
+    return V.lo >= -256 && V.hi < 768 &&
+           tri_code_lds_bytes(LA, V.alphabet, V.CB, es, R) <= (R == 1 ? kMaxLdsBytes : kTriPairLdsBudget);
 }
 
 // Write a staged row segment of len elements (es bytes each) at LDS address
@@ -89,9 +98,10 @@ __device__ __forceinline__ void store_segment(uint8_t *g, uint32_t sl, int64_t l
     }
 }
 
-template <int LA>
+template <int LA, int R>
 __global__ __launch_bounds__(kThreads) void k_tri_code(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
-                                                     int es, uint32_t rb0, uint32_t rbn, uint32_t chunks, uint32_t rpc)
+                                                       int es, uint32_t rb0, uint32_t rbn, uint32_t chunks,
+                                                       uint32_t rpc)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     uint32_t r, b;
@@ -115,45 +125,80 @@ __global__ __launch_bounds__(kThreads) void k_tri_code(DevVocab V, uint64_t idx_
         if (last < idx_begin || first >= idx_end) return;
     }
 
+    const int A = V.alphabet;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const uint32_t PB = profile_bytes(LA, V.alphabet);
+    const uint32_t PB = topk_code_profile_bytes(LA, R, A);
     const uint32_t lds0 = lds_addr_of(lds);
-    const uint32_t meta_off = 2 * PB;
-    const uint32_t stage_off = meta_off + 8u * (uint32_t)CB;
+    // per column slot: staging column (CB for padding slots) | K << 16; per
+    // group of 64 slots: the longest length
+    uint32_t *meta = reinterpret_cast<uint32_t *>(lds + 2 * PB);
+    uint8_t *gmax = reinterpret_cast<uint8_t *>(meta + CB);
+    uint16_t *wt_lds = reinterpret_cast<uint16_t *>(gmax + (((uint32_t)CB / 64u + 15u) & ~15u));
+    uint8_t *chunks_lds = reinterpret_cast<uint8_t *>(wt_lds) + wtab_lds_bytes(A);
+    const uint32_t stage_off = (uint32_t)(chunks_lds - lds) + 2u * tri_chunk_bytes(LA);
     const uint32_t SR = tri_code_stage_row((int)CB, es);
-    uint2 *meta = reinterpret_cast<uint2 *>(lds + meta_off);
-    // x = staging column (CB for padding slots) | K << 16, y = lb
+    constexpr uint32_t SW = chunk_sym_bytes(LA);
     for (int i = tid; i < CB; i += kThreads) {
         const int64_t slot = J0 + i;
         const uint32_t col = V.bcol[slot];
         const uint32_t lb = V.blen[slot];
         const _Float16 kf = (_Float16)(float)(kTriCodeBias + V.gap * (LA + (int)lb));
         const uint32_t kbits = __builtin_bit_cast(uint16_t, kf);
-        meta[i] = make_uint2((col == 0xFFFF ? (uint32_t)CB : col) | (kbits << 16), lb);
+        meta[i] = (col == 0xFFFF ? (uint32_t)CB : col) | (kbits << 16);
+        if ((i & 63) == 63) gmax[i >> 6] = (uint8_t)lb;
     }
-    const ProfileRole role = profile_role(tid, V.alphabet);
+    const bool wt_staged = A <= kLdsWtabMaxAlphabet;
+    if (wt_staged)
+        for (int i = tid; i < A * A; i += kThreads) wt_lds[i] = V.wtab[i];
+    const uint16_t *wt = wt_staged ? wt_lds : V.wtab;
+    const ProfileRole role = profile_role(tid, A);
     const int CPL = V.CB / kThreads;
     const int lane_base = wave * 64 + lane;
+    auto chunk_of = [&](uint32_t k) { return chunks_lds + ((k - pbeg) / kChunkPairs & 1) * tri_chunk_bytes(LA); };
 
-    for (uint32_t k = pbeg; k < pend + 2; ++k) {
-        if (k < pend) {
-            const int32_t a0 = V.rpairs[2 * k], a1 = V.rpairs[2 * k + 1];
-            build_profile<LA>(V.wtab, V.alphabet, reinterpret_cast<uint32_t *>(lds + (k & 1) * PB),
-                              V.bsym + (int64_t)a0 * kWordBytes, V.bsym + (int64_t)(a1 >= 0 ? a1 : a0) * kWordBytes,
-                              role);
-        }
-        if (k >= pbeg + 2) {
-            const uint32_t kk = k - 2;
+    // step s covers row pairs pbeg + R s .. + R - 1; its rows are stored two steps later
+    const uint32_t nsteps = (pend - pbeg + R - 1) / R;
+    for (uint32_t st = 0; st < nsteps + 2; ++st) {
+        const uint32_t k = pbeg + R * st;
+        if (st < nsteps) {
+            const uint32_t kc = (k - pbeg) % kChunkPairs;
+            uint8_t *chunk = chunk_of(k);
+            uint8_t *csym = chunk;
+            int32_t *cu = reinterpret_cast<int32_t *>(chunk + 2 * kChunkPairs * SW);
+            if (kc == 0) {
+                if (tid < 2 * kChunkPairs) {
+                    const uint32_t kk = k + (uint32_t)(tid >> 1);
+                    const int32_t slot = kk < pend ? V.rpairs[2 * kk + (tid & 1)] : -1;
+                    cu[tid] = slot >= 0 ? (int32_t)(I0 + V.bcol[slot]) : -1;
+                    const uint32_t *src =
+                        reinterpret_cast<const uint32_t *>(V.bsym + (int64_t)(slot >= 0 ? slot : 0) * kWordBytes);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int32_t slot = V.rpairs[2 * kk + h];
-                if (slot < 0) continue;
-                const int64_t u = I0 + V.bcol[slot];
+                    for (uint32_t q = 0; q < SW / 4; ++q)
+                        reinterpret_cast<uint32_t *>(csym + tid * SW)[q] = slot >= 0 ? src[q] : 0u;
+                }
+                __syncthreads();
+            }
+            auto wp = [&](int h) { return csym + (2 * kc + h) * SW; };
+            if constexpr (R == 1)
+                build_profile<LA>(wt, A, reinterpret_cast<uint32_t *>(lds + (st & 1) * PB), wp(0), wp(1), role);
+            else
+                build_profile2<LA>(wt, A, reinterpret_cast<uint32_t *>(lds + (st & 1) * PB), wp(0), wp(1), wp(2),
+                                   wp(3), role);
+        }
+        if (st >= 2) {
+            // store the staged rows of step st - 2 as contiguous row segments
+            const uint32_t ks = pbeg + R * (st - 2);
+            const uint32_t kc = (ks - pbeg) % kChunkPairs;
+            const int32_t *cu = reinterpret_cast<const int32_t *>(chunk_of(ks) + 2 * kChunkPairs * SW);
+#pragma unroll
+            for (int h = 0; h < 2 * R; ++h) {
+                const int64_t u = cu[2 * kc + h];
+                if (u < 0) continue;
                 const int64_t jstart = (r == b) ? u + 1 : J0;
                 const int64_t len = J1 - jstart;
                 if (len <= 0) continue;
-                const uint32_t sl = lds0 + stage_off + ((kk % 3) * 2 + h) * SR + (uint32_t)(jstart - J0) * es;
+                const uint32_t sl = lds0 + stage_off + (((st - 2) % 3) * 2 * R + h) * SR + (uint32_t)(jstart - J0) * es;
                 const uint64_t base = row_start_idx(n, u) + (uint64_t)(jstart - u - 1);
                 if (base >= idx_begin && base + (uint64_t)len <= idx_end) {
                     store_segment(static_cast<uint8_t *>(out) + (base - idx_begin) * es, sl, len, es);
@@ -171,31 +216,41 @@ __global__ __launch_bounds__(kThreads) void k_tri_code(DevVocab V, uint64_t idx_
             }
         }
         __syncthreads();
-        if (k < pend) {
-            const bool second = V.rpairs[2 * k + 1] >= 0;
-            const uint8_t *prof = lds + (k & 1) * PB;
-            const uint32_t st0 = lds0 + stage_off + (k % 3) * 2 * SR;
+        if (st < nsteps) {
+            const uint8_t *prof = lds + (st & 1) * PB;
+            const uint32_t st0 = lds0 + stage_off + (st % 3) * 2 * R * SR;
             const uint8_t *wbase = V.bsym + (J0 + lane_base) * kWordBytes;
             for (int c = 0; c < CPL; ++c) {
-                const uint2 m = meta[lane_base + c * kThreads];
-                const int lbmax_w = __builtin_amdgcn_readlane((int)m.y, 63);
+                const int sl = lane_base + c * kThreads;
+                const uint32_t m = meta[sl];
+                const int lbmax_w = __builtin_amdgcn_readfirstlane((int)gmax[sl >> 6]);
                 uint32_t bw[kWordBytes / 4];
                 load_word(bw, wbase + (int64_t)c * kThreads * kWordBytes);
-                h2 g;
-                if constexpr (LA == 0)
-                    g = h2{0, 0};
-                else
-                    g = dp_lane<LA, kWordBytes>(bw, lbmax_w, prof, profile_stride_dw<LA>() * 4u);
-                const uint32_t code = __builtin_bit_cast(uint32_t, g + as_h2(m.x).yy);
-                const uint32_t col = m.x & 0xFFFFu;
-                if (es == 1) {
-                    *lds_ptr8(st0 + col) = (uint8_t)code;
-                    if (second) *lds_ptr8(st0 + SR + col) = (uint8_t)(code >> 16);
+                h2 g[R];
+                if constexpr (LA == 0) {
+                    g[0] = h2{0, 0};
+                } else if constexpr (R == 1) {
+                    g[0] = dp_lane<LA, kWordBytes>(bw, lbmax_w, prof, profile_stride_dw<LA>() * 4u);
                 } else {
-                    const uint32_t sc = __builtin_bit_cast(
-                        uint32_t, __builtin_bit_cast(u16x2, code) - u16x2{(uint16_t)kTriCodeOrigin, (uint16_t)kTriCodeOrigin});
-                    *lds_ptr16(st0 + 2 * col) = (uint16_t)sc;
-                    if (second) *lds_ptr16(st0 + SR + 2 * col) = (uint16_t)(sc >> 16);
+                    dp_lane2<LA, kWordBytes, profile2_off_b(LA)>(bw, lbmax_w, prof, profile2_stride_dw(LA) * 4u,
+                                                                g[0], g[1]);
+                }
+                const uint32_t col = m & 0xFFFFu;
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const uint32_t code = __builtin_bit_cast(uint32_t, g[q] + as_h2(m).yy);
+                    const uint32_t row = st0 + 2 * q * SR;   // the staged rows of this pair
+                    // absent rows stage like present ones and are never stored
+                    if (es == 1) {
+                        *lds_ptr8(row + col) = (uint8_t)code;
+                        *lds_ptr8(row + SR + col) = (uint8_t)(code >> 16);
+                    } else {
+                        const uint32_t sc = __builtin_bit_cast(
+                            uint32_t, __builtin_bit_cast(u16x2, code) -
+                                          u16x2{(uint16_t)kTriCodeOrigin, (uint16_t)kTriCodeOrigin});
+                        *lds_ptr16(row + 2 * col) = (uint16_t)sc;
+                        *lds_ptr16(row + SR + 2 * col) = (uint16_t)(sc >> 16);
+                    }
                 }
             }
         }

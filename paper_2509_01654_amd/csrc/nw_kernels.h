@@ -15,7 +15,8 @@ constexpr int kNumClass8 = 7;
 
 struct KernelTables {
     const void *tri[kMaxLen + 1];
-    const void *tri_code[kMaxLen + 1];   // the same with score codes and dword stores
+    const void *tri_code1[kMaxLen + 1];  // the same with score codes and dword stores, one row pair a step
+    const void *tri_code2[kMaxLen + 1];  // two row pairs a step (rows 1 .. 16; else NULL)
     const void *query[kMaxLen + 1];
     const void *topk[kMaxLen + 1];
     const void *topk_code[kMaxLen + 1];  // the same with the score-code epilogue
