@@ -12,6 +12,7 @@
 // always drains.
 #pragma once
 
+#include "k_tri_code.h"
 #include "k_tri_tiled.h"
 
 namespace nw {
@@ -37,10 +38,25 @@ __device__ __forceinline__ void tri_tile_dispatch(int la, const DevVocab &V, uin
     }
 }
 
+// The same for the score-code tile (tri_tile_code, one row pair a step).
+template <int L, int HI>
+__device__ __forceinline__ void tri_tile_code_dispatch(int la, const DevVocab &V, uint32_t r, uint32_t b,
+                                                       uint32_t pbeg, uint32_t pend, void *out, int es, uint8_t *lds)
+{
+    if constexpr (L <= HI) {
+        if (la == L)
+            tri_tile_code<L, 1>(V, r, b, pbeg, pend, 0, ~0ull, out, es, lds);
+        else
+            tri_tile_code_dispatch<L + 1, HI>(la, V, r, b, pbeg, pend, out, es, lds);
+    }
+}
+
+// code_es = 1 or 2: every dictionary's scores fit the score-code tile, which
+// stores es-byte scores; 0: the plain tile with out_kind.
 template <int LO, int HI>
 __global__ __launch_bounds__(kThreads) void k_tri_persist(const DevVocab *vocabs, const BatchItem *items,
                                                           uint32_t nitems, uint32_t *counter, void *const *outs,
-                                                          int out_kind)
+                                                          int out_kind, int code_es)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_item;
@@ -52,8 +68,11 @@ __global__ __launch_bounds__(kThreads) void k_tri_persist(const DevVocab *vocabs
         if (it >= nitems) break;
         const BatchItem I = items[it];
         const DevVocab V = vocabs[I.vocab];
-        tri_tile_dispatch<LO, HI>(I.la, V, I.r, I.b, I.pbeg, I.pend, 0, ~0ull, outs[I.vocab], out_kind, EdgeSink{},
-                                  lds);
+        if (code_es)
+            tri_tile_code_dispatch<LO, HI>(I.la, V, I.r, I.b, I.pbeg, I.pend, outs[I.vocab], code_es, lds);
+        else
+            tri_tile_dispatch<LO, HI>(I.la, V, I.r, I.b, I.pbeg, I.pend, 0, ~0ull, outs[I.vocab], out_kind,
+                                      EdgeSink{}, lds);
     }
 }
 

@@ -98,20 +98,15 @@ __device__ __forceinline__ void store_segment(uint8_t *g, uint32_t sl, int64_t l
     }
 }
 
+// One tile: row pairs [pbeg, pend) of block r (all of length LA) against the
+// columns of block b, scores of pair indices in [idx_begin, idx_end) stored
+// to out (es bytes each).  Every thread of the workgroup calls it; it ends
+// with a barrier, so the caller may reuse the LDS afterwards.
 template <int LA, int R>
-__global__ __launch_bounds__(kThreads) void k_tri_code(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
-                                                       int es, uint32_t rb0, uint32_t rbn, uint32_t chunks,
-                                                       uint32_t rpc)
+__device__ __forceinline__ void tri_tile_code(const DevVocab &V, uint32_t r, uint32_t b, uint32_t pbeg, uint32_t pend,
+                                              uint64_t idx_begin, uint64_t idx_end, void *out, int es, uint8_t *lds)
 {
-    extern __shared__ __align__(16) uint8_t lds[];
-    uint32_t r, b;
-    if (!tile_block_pair(blockIdx.x / chunks, rb0, rbn, V.nb, r, b)) return;
-    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
-    const uint64_t pbeg64 = (uint64_t)rpo[0] + (uint64_t)(blockIdx.x % chunks) * rpc;
-    if (pbeg64 >= rpo[1]) return;
-    const uint32_t pbeg = (uint32_t)pbeg64;
-    const uint32_t pend = rpo[1] - pbeg <= rpc ? rpo[1] : pbeg + rpc;
-
+    if (pbeg >= pend) return;
     const int64_t n = V.n, CB = V.CB;
     const int64_t I0 = (int64_t)r * CB, I1 = min(I0 + CB, n);
     const int64_t J0 = (int64_t)b * CB, J1 = min(J0 + CB, n);
@@ -255,6 +250,24 @@ __global__ __launch_bounds__(kThreads) void k_tri_code(DevVocab V, uint64_t idx_
             }
         }
     }
+}
+
+// Workgroup = tile * chunks + chunk: a tile's row pairs of length LA are
+// split into `chunks` runs of at most rpc row pairs (rpc a multiple of R).
+template <int LA, int R>
+__global__ __launch_bounds__(kThreads) void k_tri_code(DevVocab V, uint64_t idx_begin, uint64_t idx_end, void *out,
+                                                       int es, uint32_t rb0, uint32_t rbn, uint32_t chunks,
+                                                       uint32_t rpc)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t r, b;
+    if (!tile_block_pair(blockIdx.x / chunks, rb0, rbn, V.nb, r, b)) return;
+    const uint32_t *rpo = V.rp_off + (size_t)r * (V.lmax + 1) + LA;
+    const uint64_t pbeg64 = (uint64_t)rpo[0] + (uint64_t)(blockIdx.x % chunks) * rpc;
+    if (pbeg64 >= rpo[1]) return;
+    const uint32_t pbeg = (uint32_t)pbeg64;
+    const uint32_t pend = rpo[1] - pbeg <= rpc ? rpo[1] : pbeg + rpc;
+    tri_tile_code<LA, R>(V, r, b, pbeg, pend, idx_begin, idx_end, out, es, lds);
 }
 
 }  // namespace nw

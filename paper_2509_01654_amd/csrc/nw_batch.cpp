@@ -40,6 +40,7 @@ struct Plan {
     std::vector<BatchItem> items;               // grouped by class, heaviest first
     std::vector<uint32_t> class_off;            // [nclass + 1]
     std::vector<uint32_t> class_lds;            // dynamic LDS per class
+    int code_es = 0;                            // score-code tiles storing es bytes, or 0: plain tiles
     int width = 8;
     uint64_t ws_bytes = 0;
     uint64_t off_vocabs = 0, off_outs = 0, off_counters = 0, off_items = 0;
@@ -48,7 +49,7 @@ struct Plan {
 int num_classes(int width) { return width == 0 ? 0 : width == 1 ? kMaxLen + 1 : kNumClass8; }
 int class_of(int la, int width) { return width == 1 ? la : la / 8; }
 
-Plan make_plan(const nw_vocab *const *v, uint32_t nv, const nw_batch_options &o)
+Plan make_plan(const nw_vocab *const *v, uint32_t nv, const nw_batch_options &o, int es)
 {
     Plan P;
     P.width = o.class_width == 0 ? 0 : o.class_width == 1 ? 1 : 8;
@@ -60,6 +61,12 @@ Plan make_plan(const nw_vocab *const *v, uint32_t nv, const nw_batch_options &o)
     }
     std::vector<std::vector<std::pair<double, BatchItem>>> cls(nc);
     P.class_lds.assign(nc, 0);
+    // the score-code tiles when every dictionary's scores fit their window
+    // and every class's buffers fit
+    P.code_es = es;
+    for (uint32_t vi = 0; vi < nv; ++vi)
+        for (int la = 0; la <= v[vi]->dev.lmax; ++la)
+            if (!tri_code_applies(v[vi]->dev, la, es, 1)) P.code_es = 0;
     for (uint32_t vi = 0; vi < nv; ++vi) {
         const nw_vocab &V = *v[vi];
         const DevVocab &D = V.dev;
@@ -69,7 +76,8 @@ Plan make_plan(const nw_vocab *const *v, uint32_t nv, const nw_batch_options &o)
         for (uint64_t u = 0; u < V.n; ++u) bcells[u / D.CB] += V.h_clen[u];
         for (int la = 0; la <= LM; ++la) {
             const int c = class_of(la, P.width);
-            P.class_lds[c] = std::max<uint32_t>(P.class_lds[c], tri_lds_bytes(la, D.alphabet, D.CB));
+            P.class_lds[c] = std::max<uint32_t>(P.class_lds[c], P.code_es ? tri_code_lds_bytes(la, D.alphabet, D.CB, es, 1)
+                                                                            : tri_lds_bytes(la, D.alphabet, D.CB));
         }
         for (uint32_t b = 0; b < (uint32_t)D.nb; ++b)
             for (uint32_t r = 0; r <= b; ++r)
@@ -173,8 +181,9 @@ struct nw_batch {
             const BatchItem *it = items + plan.class_off[c];
             uint32_t *ctr = counters + c;
             int kind = out_kind;
+            int code_es = plan.code_es;
             uint32_t nn = n;
-            void *args[] = {&vocabs, &it, &nn, &ctr, &outs, &kind};
+            void *args[] = {&vocabs, &it, &nn, &ctr, &outs, &kind, &code_es};
             if ((e = fork.launch(fn, dim3(grid), dim3(kThreads), lds, args)) != hipSuccess) return e;
         }
         return fork.end();
@@ -222,7 +231,7 @@ int nw_batch_workspace_bytes(const nw_vocab *const *v, uint32_t nv, const nw_bat
 {
     if (!v || !nv || !opt || !bytes) return fail(NW_EINVAL, "NULL argument");
     if (nv > 65535) return fail(NW_EINVAL, "at most 65535 dictionaries");
-    *bytes = make_plan(v, nv, *opt).ws_bytes;
+    *bytes = make_plan(v, nv, *opt, 2).ws_bytes;   // the items do not depend on the output type
     return ok();
 }
 
@@ -246,7 +255,7 @@ int nw_batch_create(const nw_vocab *const *v, uint32_t nv, void *const *d_outs, 
     B->v.assign(v, v + nv);
     B->outs.assign(d_outs, d_outs + nv);
     B->opt = *opt;
-    B->plan = make_plan(v, nv, *opt);
+    B->plan = make_plan(v, nv, *opt, dt == NW_I8 ? 1 : 2);
     B->out_kind = dt == NW_I8 ? OUT_I8 : OUT_I16;
     B->ws = static_cast<uint8_t *>(d_ws);
     if (ws_bytes < B->plan.ws_bytes) {
