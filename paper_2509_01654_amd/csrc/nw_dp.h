@@ -55,12 +55,36 @@ __device__ __forceinline__ uint32_t sym_at(const uint32_t (&bw)[NW], int j)
     return __builtin_amdgcn_ubfe(bw[j >> 2], (j & 3) * 8, 8);
 }
 
-// The NQ 16-byte units of a profile row, QS bytes apart.
+// LDS byte addresses as plain integers: the address of a __shared__ object,
+// and typed pointers at an address.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
+__device__ __forceinline__ uint32_t lds_addr_of(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)p;
+}
+__device__ __forceinline__ lds_u32 *lds_ptr(uint32_t addr) { return (lds_u32 *)(uintptr_t)addr; }
+__device__ __forceinline__ lds_u16 *lds_ptr16(uint32_t addr) { return (lds_u16 *)(uintptr_t)addr; }
+__device__ __forceinline__ lds_u8 *lds_ptr8(uint32_t addr) { return (lds_u8 *)(uintptr_t)addr; }
+
+// A wave-uniform value kept in a vector register: the profile base then
+// enters the per-column address multiply-add as its vector operand, beside
+// the row stride in a scalar register (one multiply-add per column, with no
+// copy of the base into a vector register each time).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// The NQ 16-byte units of the profile row at LDS address `row`, QS bytes apart.
 template <int NQ, int QS = 16>
-__device__ __forceinline__ void load_row(u32x4 (&dst)[NQ], const uint8_t *row)
+__device__ __forceinline__ void load_row(u32x4 (&dst)[NQ], uint32_t row)
 {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) dst[q] = *reinterpret_cast<const u32x4 *>(row + q * QS);
+    for (int q = 0; q < NQ; ++q) dst[q] = *(const lds_u32x4 *)(uintptr_t)(row + q * QS);
 }
 
 // Run the DP of two row words (profile `prof`, LA symbols each) against the
@@ -104,8 +128,9 @@ __device__ __forceinline__ h2 dp_lane(const uint32_t (&bw)[LBMAX / 4], int lbmax
 #pragma unroll
     for (int i = 0; i < LA; ++i) col[i] = h2{0, 0};
 
+    const uint32_t pb = in_vgpr(lds_addr_of(prof));
     u32x4 wa[NQ], wb[NQ];
-    load_row<NQ, QS>(wa, prof + sym_at(bw, 0) * stride_b);
+    load_row<NQ, QS>(wa, pb + sym_at(bw, 0) * stride_b);
     static_for<0, LBMAX>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j >= lbmax_w) return false;
@@ -113,7 +138,7 @@ __device__ __forceinline__ h2 dp_lane(const uint32_t (&bw)[LBMAX / 4], int lbmax
         u32x4(&nxt)[NQ] = (j & 1) ? wa : wb;
         // prefetch the profile row of the next column (past the end of a word
         // the bytes are the sentinel, a valid row, so the read is in bounds)
-        if constexpr (j + 1 < LBMAX) load_row<NQ, QS>(nxt, prof + sym_at(bw, j + 1) * stride_b);
+        if constexpr (j + 1 < LBMAX) load_row<NQ, QS>(nxt, pb + sym_at(bw, j + 1) * stride_b);
         // column j+1 of G: cell i+1 = max3(G[i][j] + w, G[i+1][j], G[i][j+1])
         h2 t = as_h2(cur[0][0]);   // G[0][j] = 0, plus w of row 0
         h2 up = h2{0, 0};          // G[0][j+1] = 0
@@ -157,11 +182,12 @@ __device__ __forceinline__ void dp_lane2(const uint32_t (&bw)[LBMAX / 4], int lb
 #pragma unroll
     for (int i = 0; i < LA; ++i) ca[i] = cb[i] = h2{0, 0};
 
+    const uint32_t pb = in_vgpr(lds_addr_of(prof));
     u32x4 wa[NQ], wb[NQ];
     static_for<0, LBMAX>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j >= lbmax_w) return false;
-        const uint8_t *row = prof + sym_at(bw, j) * stride_b;
+        const uint32_t row = pb + sym_at(bw, j) * stride_b;
         load_row(wa, row);
         load_row(wb, row + OFF_B);
         if constexpr (j == 0) {
@@ -192,22 +218,5 @@ __device__ __forceinline__ void dp_lane2(const uint32_t (&bw)[LBMAX / 4], int lb
     ga = ca[LA - 1];
     gb = cb[LA - 1];
 }
-
-}  // namespace nw
-
-namespace nw {
-
-// LDS byte addresses as plain integers: the address of a __shared__ object,
-// and typed pointers at an address.
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-typedef __attribute__((address_space(3))) uint16_t lds_u16;
-typedef __attribute__((address_space(3))) uint8_t lds_u8;
-__device__ __forceinline__ uint32_t lds_addr_of(const void *p)
-{
-    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)p;
-}
-__device__ __forceinline__ lds_u32 *lds_ptr(uint32_t addr) { return (lds_u32 *)(uintptr_t)addr; }
-__device__ __forceinline__ lds_u16 *lds_ptr16(uint32_t addr) { return (lds_u16 *)(uintptr_t)addr; }
-__device__ __forceinline__ lds_u8 *lds_ptr8(uint32_t addr) { return (lds_u8 *)(uintptr_t)addr; }
 
 }  // namespace nw
