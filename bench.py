@@ -66,7 +66,7 @@ COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "topk_main_paper600k_counters.m
 MAIN_PASS_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "nw_topk.h", "k_topk.h", "k_topk_code.h", "k_query.h",
                      "k_launch.hip", "k_inst.hip", "nw_api.cpp"]
 # the same for the 50,000-word int8 triangle (k_tri_code)
-TRI_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "tri_tiled_mid50k_counters.md")
+TRI_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "tri_code_mid50k_counters.md")
 TRI_SOURCES = ["nw_internal.h", "nw_dp.h", "nw_tile_common.h", "k_tri_tiled.h", "k_tri_code.h", "k_launch.hip", "k_inst.hip",
                "nw_api.cpp"]
 
