@@ -57,11 +57,17 @@ int refuse_capture(hipStream_t stream, const char *call)
 }
 
 // Block size: small dictionaries need many workgroups; large ones amortise
-// the per-row-pair work (profile build, barrier) over more lane words.
-int choose_block(uint64_t n)
+// the per-step work (profile build, barrier, row stores) over more lane
+// words, which matters most for short rows (a step's DP is short): up to
+// 24-symbol words, blocks of 2048 from 32k words on (50k-word triangle
+// 3.15 -> 2.98 ms); with longer words 1024 up to 131k words (2048 made the
+// batched workload's 40k..100k-word dictionaries of words up to 31..48
+// symbols 7 % slower).
+int choose_block(uint64_t n, uint32_t max_len)
 {
     if (n <= 16384) return 256;
-    if (n <= 131072) return 1024;
+    if (n <= 32768) return 1024;
+    if (n <= 131072 && max_len > 24) return 1024;
     return 2048;
 }
 
@@ -84,8 +90,7 @@ struct Layout {
 Layout make_layout(uint64_t n, uint32_t max_len)
 {
     Layout L{};
-    L.CB = choose_block(n);
-    (void)max_len;
+    L.CB = choose_block(n, max_len);
     L.WB = max_len <= (uint32_t)kMaxLen ? kWordBytes : 256;   // whole 16-byte units
     L.nb = (int)((n + L.CB - 1) / L.CB);
     const uint64_t slots = (uint64_t)L.nb * L.CB;
@@ -140,7 +145,7 @@ struct TopkWs {
     uint32_t cap;
 };
 
-uint32_t topk_cap(uint64_t n, uint32_t k)
+uint32_t topk_cap(uint64_t n, uint64_t CB, uint32_t k)
 {
     // Expected candidates of one word.  The probe threshold is the (k+1)-th
     // best key over M probe words and ranks about all = (k+1)(n-1)/M among
@@ -152,7 +157,6 @@ uint32_t topk_cap(uint64_t n, uint32_t k)
     // the sum, plus a margin, bounds the list in practice; a word past the
     // capacity is recomputed exactly.
     const uint64_t M = num_probes(n);
-    const uint64_t CB = (uint64_t)choose_block(n);
     const uint64_t nb = std::max<uint64_t>(1, (n + CB - 1) / CB);
     const double f = std::min(1.0, (double)((nb + kPhasePeriod - 1) / kPhasePeriod) / (double)nb);
     const double all = M >= n ? (double)(k + 1) : (double)(k + 1) * (double)(n - 1) / (double)M;
@@ -172,10 +176,10 @@ uint32_t topk_cap(uint64_t n, uint32_t k)
     return (uint32_t)cap;
 }
 
-TopkWs topk_ws(uint64_t n, uint32_t k)
+TopkWs topk_ws(uint64_t n, uint64_t CB, uint32_t k)
 {
     TopkWs w{};
-    w.cap = topk_cap(n, k);
+    w.cap = topk_cap(n, CB, k);
     uint64_t o = 0;
     auto take = [&](uint64_t bytes) {
         uint64_t at = o;
@@ -678,7 +682,7 @@ int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes)
 {
     if (!v || !bytes) return fail(NW_EINVAL, "NULL argument");
     if (k < 1 || k > 63) return fail(NW_EINVAL, "k = %u outside 1..63", k);
-    *bytes = topk_ws(v->n, k).total;
+    *bytes = topk_ws(v->n, (uint64_t)v->dev.CB, k).total;
     return ok();
 }
 
@@ -693,7 +697,7 @@ int check_topk_args(const nw_vocab *v, uint32_t k, const int16_t *d_score, const
     if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
     if (v->max_len > (uint32_t)kMaxLen)
         return fail(NW_EINVAL, "top-k supports words of at most %d symbols (this dictionary has %u)", kMaxLen, v->max_len);
-    const TopkWs W = topk_ws(v->n, k);
+    const TopkWs W = topk_ws(v->n, (uint64_t)v->dev.CB, k);
     if (v->n > 0 && (!d_score || !d_index)) return fail(NW_EINVAL, "d_score / d_index is NULL");
     if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
     if (ws_bytes < W.total)
@@ -708,7 +712,7 @@ int topk_enqueue(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_ind
                  hipStream_t st)
 {
     const uint64_t n = v->n;
-    const TopkWs W = topk_ws(n, k);
+    const TopkWs W = topk_ws(n, (uint64_t)v->dev.CB, k);
     const DevVocab &D = v->dev;
     const int nbins = v->hi - v->lo + 1;
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
@@ -779,7 +783,7 @@ int topk_enqueue(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_ind
 int topk_finish(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, void *d_ws, hipStream_t st)
 {
     const uint64_t n = v->n;
-    const TopkWs W = topk_ws(n, k);
+    const TopkWs W = topk_ws(n, (uint64_t)v->dev.CB, k);
     nw_vocab *vm = const_cast<nw_vocab *>(v);
     const DevVocab &D = v->dev;
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
