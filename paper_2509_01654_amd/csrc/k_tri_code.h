@@ -42,14 +42,13 @@ __host__ __device__ constexpr uint32_t tri_code_stage_row(int CB, int es) { retu
 // at least four workgroups per CU; one otherwise.
 constexpr uint32_t kTriPairLdsBudget = 40u * 1024u;
 // Dynamic LDS: two profile buffers, 4 bytes of metadata per column slot, the
-// longest length of each group of 64 slots, the similarity table, two
-// row-pair chunks (symbols and caller indices) and three staged steps of
-// 2R rows each.
+// longest length of each group of 64 slots, two row-pair chunks (symbols and
+// caller indices) and three staged steps of 2R rows each.
 __host__ __device__ constexpr uint32_t tri_chunk_bytes(int LA) { return 2u * kChunkPairs * (chunk_sym_bytes(LA) + 4u); }
 __host__ __device__ constexpr uint32_t tri_code_lds_bytes(int LA, int alphabet, int CB, int es, int R)
 {
     return 2u * topk_code_profile_bytes(LA, R, alphabet) + 4u * (uint32_t)CB + (((uint32_t)CB / 64u + 15u) & ~15u) +
-           wtab_lds_bytes(alphabet) + 2u * tri_chunk_bytes(LA) + 3u * 2u * (uint32_t)R * tri_code_stage_row(CB, es);
+           2u * tri_chunk_bytes(LA) + 3u * 2u * (uint32_t)R * tri_code_stage_row(CB, es);
 }
 
 // Does a triangle call on this dictionary take k_tri_code<LA, R>?  Every
@@ -129,8 +128,7 @@ __device__ __forceinline__ void tri_tile_code(const DevVocab &V, uint32_t r, uin
     // group of 64 slots: the longest length
     uint32_t *meta = reinterpret_cast<uint32_t *>(lds + 2 * PB);
     uint8_t *gmax = reinterpret_cast<uint8_t *>(meta + CB);
-    uint16_t *wt_lds = reinterpret_cast<uint16_t *>(gmax + (((uint32_t)CB / 64u + 15u) & ~15u));
-    uint8_t *chunks_lds = reinterpret_cast<uint8_t *>(wt_lds) + wtab_lds_bytes(A);
+    uint8_t *chunks_lds = gmax + (((uint32_t)CB / 64u + 15u) & ~15u);
     const uint32_t stage_off = (uint32_t)(chunks_lds - lds) + 2u * tri_chunk_bytes(LA);
     const uint32_t SR = tri_code_stage_row((int)CB, es);
     constexpr uint32_t SW = chunk_sym_bytes(LA);
@@ -143,10 +141,9 @@ __device__ __forceinline__ void tri_tile_code(const DevVocab &V, uint32_t r, uin
         meta[i] = (col == 0xFFFF ? (uint32_t)CB : col) | (kbits << 16);
         if ((i & 63) == 63) gmax[i >> 6] = (uint8_t)lb;
     }
-    const bool wt_staged = A <= kLdsWtabMaxAlphabet;
-    if (wt_staged)
-        for (int i = tid; i < A * A; i += kThreads) wt_lds[i] = V.wtab[i];
-    const uint16_t *wt = wt_staged ? wt_lds : V.wtab;
+    // the weight table stays in global memory (cached): in LDS it would cost
+    // a workgroup per CU, which the triangle's short steps need more
+    const uint16_t *wt = V.wtab;
     const ProfileRole role = profile_role(tid, A);
     const int CPL = V.CB / kThreads;
     const int lane_base = wave * 64 + lane;
