@@ -139,7 +139,7 @@ static uint32_t tile_chunks(uint64_t tiles, uint32_t maxrp)
 {
     constexpr uint64_t kTargetWorkgroups = 256 * 6 * 4;
     constexpr uint64_t kSplitBelow = 2048;
-    constexpr uint32_t kMinRowPairs = 8;
+    constexpr uint32_t kMinRowPairs = 16;
     if (tiles >= kSplitBelow) return 1;
     const uint32_t want = (uint32_t)((kTargetWorkgroups + tiles - 1) / tiles);
     return std::max<uint32_t>(1, std::min(want, maxrp / kMinRowPairs));
