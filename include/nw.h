@@ -85,9 +85,11 @@ int nw_max_word_length(void);
  * the longest being max_len.  NW_EINVAL if max_len exceeds the maximum. */
 int nw_vocab_bytes(uint64_t n, uint64_t total_symbols, uint32_t max_len, uint64_t *dev_bytes);
 
-/* Validate the words and the scoring, bucket the words by length (stable
- * length sort inside fixed-size blocks of the caller's order) and copy the
- * packed layout into d_mem (>= nw_vocab_bytes(...) bytes, 256-byte aligned).
+/* Validate the words and the scoring, bucket the words by length (inside
+ * fixed-size blocks of the caller's order, sorted by length and, within a
+ * length, lexicographically) and copy the packed layout into d_mem
+ * (>= nw_vocab_bytes(...) bytes, 256-byte aligned).  The order is internal:
+ * every result is in the caller's word order.
  * Synchronous: returns after the copy has completed on hip_stream.
  * Errors: NW_EINVAL (n >= 2^31, a symbol >= alphabet, a word longer than
  * nw_max_word_length(), gap > 0, alphabet outside 1..255), NW_ERANGE (the
