@@ -6,6 +6,7 @@
 
 #include "k_batch.h"
 #include "k_edges.h"
+#include "k_probe.h"
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_topk_code.h"
@@ -34,6 +35,7 @@ static void fill(KernelTables &t, std::integer_sequence<int, Is...>)
     ((t.tri_code1[LO + Is] = reinterpret_cast<const void *>(&k_tri_code<LO + Is, 1>)), ...);
     ((t.tri_code2[LO + Is] = tri_code2_kernel<LO + Is>()), ...);
     ((t.query[LO + Is] = reinterpret_cast<const void *>(&k_query_tiled<LO + Is>)), ...);
+    ((t.probe_thr[LO + Is] = reinterpret_cast<const void *>(&k_probe_thr<LO + Is>)), ...);
     ((t.topk[LO + Is] = reinterpret_cast<const void *>(&k_topk_tiled<LO + Is>)), ...);
     ((t.topk_code[LO + Is] = reinterpret_cast<const void *>(&k_topk_code<LO + Is, topk_code_pairs(LO + Is)>)), ...);
     ((t.edges[LO + Is] = reinterpret_cast<const void *>(&k_edges_tiled<LO + Is>)), ...);

@@ -12,6 +12,7 @@
 #include "k_batch.h"
 #include "k_diag.h"
 #include "k_edges.h"
+#include "k_probe.h"
 #include "k_query.h"
 #include "k_topk.h"
 #include "k_topk_code.h"
@@ -369,6 +370,59 @@ hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_of
         if (e != hipSuccess) return e;
     }
     return fork_streams ? fork.end() : hipSuccess;
+}
+
+// NW_PREPASS=lists keeps the list pre-pass (k_query_tiled + merge) where the
+// selection would apply (both give the same keys; for comparisons).
+static bool list_prepass_only()
+{
+    static const bool only = [] {
+        const char *e = std::getenv("NW_PREPASS");
+        return e && std::strcmp(e, "lists") == 0;
+    }();
+    return only;
+}
+
+bool probe_thr_applies(const DevVocab &V)
+{
+    return !list_prepass_only() && V.hi - V.lo <= kProbeMaxCode && V.pslots <= kProbeMaxSlots &&
+           probe_lds_bytes(kMaxLen, V.alphabet, V.pslots) <= 65536u;
+}
+
+hipError_t launch_probe_thr(const DevVocab &V, const RowSet &R, const uint32_t *h_off, int m, uint64_t *thr,
+                            hipStream_t stream)
+{
+    if (!probe_thr_applies(V)) return hipErrorNotSupported;
+    const KernelTables &tab = kernel_tables();
+    StreamFork fork(stream);
+    hipError_t ef = fork.begin();
+    if (ef != hipSuccess) return ef;
+    const int rpw = 1;   // a workgroup per row pair: measured best of 1, 2, 4, 8 and 16
+    for (int LA = 0; LA <= kMaxLen; ++LA) {
+        const uint32_t np = h_off[LA + 1] - h_off[LA];
+        if (np == 0) continue;
+        ProbeArgs Q;
+        Q.R = R;
+        Q.C.sym = V.psym;
+        Q.C.len = V.plen;
+        Q.C.orig = V.porig;
+        Q.C.nslots = V.pslots;
+        Q.rank = V.prank;
+        Q.wtab = V.wtab;
+        Q.alphabet = V.alphabet;
+        Q.gap = V.gap;
+        Q.lo = V.lo;
+        Q.m = m;
+        Q.rpw = rpw;
+        Q.n = V.n;
+        Q.nprobe = V.nprobe;
+        Q.thr = thr;
+        void *args[] = {&Q};
+        hipError_t e = launch_dyn(tab.probe_thr[LA], dim3((np + rpw - 1) / rpw), probe_lds_bytes(LA, V.alphabet, V.pslots),
+                                  fork, args);
+        if (e != hipSuccess) return e;
+    }
+    return fork.end();
 }
 
 hipError_t launch_merge(const uint64_t *partial, int P, int kin, int64_t rows, int kout, int lo, int16_t *score,

@@ -82,7 +82,7 @@ constexpr int kPhasePeriod = 8;
 // Byte offsets of every region inside d_mem.
 struct Layout {
     uint64_t csym, clen, bsym, blen, bcol, rpairs, rp_off, dpairs, dp_off, wtab, submat, borig, gpairs, gp_off, psym, plen,
-        porig, total;
+        porig, prank, total;
     int CB, WB, nb;
     uint64_t nprobe, pslots;
 };
@@ -120,6 +120,7 @@ Layout make_layout(uint64_t n, uint32_t max_len)
     L.psym = take(L.pslots * L.WB);
     L.plen = take(L.pslots);
     L.porig = take(L.pslots * 4);
+    L.prank = take(L.pslots * 2);
     L.total = o;
     return L;
 }
@@ -391,6 +392,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     uint8_t *psym = img.data() + L.psym;
     uint8_t *plen = img.data() + L.plen;
     int32_t *porig = reinterpret_cast<int32_t *>(img.data() + L.porig);
+    uint16_t *prank = reinterpret_cast<uint16_t *>(img.data() + L.prank);
     uint8_t *csym = img.data() + L.csym;
     uint8_t *clen = img.data() + L.clen;
     uint8_t *bsym = img.data() + L.bsym;
@@ -491,18 +493,18 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     }
     // probe subset: caller indices floor(i*n/M), sorted by length, padding slots first
     {
+        // (length, rank i); u = floor(i n / M) rises with i, so this is (length, u)
         std::vector<std::pair<int, int64_t>> pr;
-        for (uint64_t i = 0; i < L.nprobe; ++i) {
-            const int64_t u = (int64_t)(i * n / L.nprobe);
-            pr.push_back({clen[u], u});
-        }
+        for (uint64_t i = 0; i < L.nprobe; ++i) pr.push_back({clen[i * n / L.nprobe], (int64_t)i});
         std::stable_sort(pr.begin(), pr.end());
         uint64_t s = 0;
-        for (; s < L.pslots - L.nprobe; ++s) { plen[s] = 0; porig[s] = -1; }
+        for (; s < L.pslots - L.nprobe; ++s) { plen[s] = 0; porig[s] = -1; prank[s] = 0; }
         for (auto &e : pr) {
+            const int64_t u = (int64_t)((uint64_t)e.second * n / L.nprobe);
             plen[s] = (uint8_t)e.first;
-            porig[s] = (int32_t)e.second;
-            if (e.first) std::memcpy(psym + s * L.WB, csym + e.second * L.WB, e.first);
+            porig[s] = (int32_t)u;
+            prank[s] = (uint16_t)e.second;
+            if (e.first) std::memcpy(psym + s * L.WB, csym + u * L.WB, e.first);
             ++s;
         }
     }
@@ -548,6 +550,7 @@ int nw_load_vocab(const uint8_t *h_symbols, const uint64_t *h_offsets, uint64_t 
     D.psym = base + L.psym;
     D.plen = base + L.plen;
     D.porig = reinterpret_cast<const int32_t *>(base + L.porig);
+    D.prank = reinterpret_cast<const uint16_t *>(base + L.prank);
     D.pslots = (int64_t)L.pslots;
     D.nprobe = (int32_t)L.nprobe;
     D.lo = (int32_t)lo;
@@ -742,10 +745,15 @@ int topk_enqueue(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_ind
     P.len = D.plen;
     P.orig = D.porig;
     P.nslots = D.pslots;
-    if ((e = launch_query(D, R, v->h_gp_off.data(), P, (int)k + 1, 1, partial, st, true)) != hipSuccess)
-        return dev_fail(e, "launching the threshold pre-pass");
-    if ((e = launch_merge(partial, query_lists(1), (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
-        return dev_fail(e, "launching the threshold merge");
+    if (probe_thr_applies(D)) {   // byte-wide score codes: selection, no lists
+        if ((e = launch_probe_thr(D, R, v->h_gp_off.data(), (int)k + 1, thr, st)) != hipSuccess)
+            return dev_fail(e, "launching the threshold pre-pass");
+    } else {
+        if ((e = launch_query(D, R, v->h_gp_off.data(), P, (int)k + 1, 1, partial, st, true)) != hipSuccess)
+            return dev_fail(e, "launching the threshold pre-pass");
+        if ((e = launch_merge(partial, query_lists(1), (int)k + 1, (int64_t)n, (int)k + 1, D.lo, nullptr, nullptr, thr, (int)k + 1, st)) != hipSuccess)
+            return dev_fail(e, "launching the threshold merge");
+    }
     if ((e = hipEventRecord(vm->ev[1], st)) != hipSuccess) return dev_fail(e, "recording a timing event");
     // 2. every unordered pair once: candidates for both endpoints, histogram.
     // Two phases: block pairs with (b - r) mod 8 == 0 first -- every word meets

@@ -71,6 +71,7 @@ struct DevVocab {
     const uint8_t *psym;        // probe words [pslots*WB]
     const uint8_t *plen;        // [pslots]
     const int32_t *porig;       // [pslots]
+    const uint16_t *prank;      // [pslots] rank i of each probe slot (0 for padding)
     int64_t pslots;
     int32_t nprobe;
     int32_t lo, hi;             // score bounds
@@ -146,6 +147,14 @@ hipError_t launch_query(const DevVocab &V, const RowSet &R, const uint32_t *h_of
 // and/or the key of rank `rank`).
 hipError_t launch_merge(const uint64_t *partial, int P, int kin, int64_t rows, int kout, int lo, int16_t *score,
                         int32_t *index, uint64_t *thr, int rank, hipStream_t stream);
+
+// The threshold pre-pass of the all-pairs top-k by selection (k_probe.h):
+// thr[u] = the key of rank m of every word u of R against V's probe subset.
+// Returns hipErrorNotSupported, launching nothing, when probe_thr_applies(V)
+// is false.
+bool probe_thr_applies(const DevVocab &V);
+hipError_t launch_probe_thr(const DevVocab &V, const RowSet &R, const uint32_t *h_off, int m, uint64_t *thr,
+                            hipStream_t stream);
 
 // Write recomputed lists: for t < B, the first k entries of (qs, qi)[t][0..kq)
 // whose index is not words[t] go to score/index[words[t]][0..k), padded with

@@ -18,6 +18,7 @@ struct KernelTables {
     const void *tri_code1[kMaxLen + 1];  // the same with score codes and dword stores, one row pair a step
     const void *tri_code2[kMaxLen + 1];  // two row pairs a step (rows 1 .. 16; else NULL)
     const void *query[kMaxLen + 1];
+    const void *probe_thr[kMaxLen + 1];  // threshold pre-pass by selection
     const void *topk[kMaxLen + 1];
     const void *topk_code[kMaxLen + 1];  // the same with the score-code epilogue
     const void *edges[kMaxLen + 1];      // threshold edge emitter
