@@ -177,7 +177,9 @@ uint32_t topk_cap(uint64_t n, uint64_t CB, uint32_t k)
     return (uint32_t)cap;
 }
 
-TopkWs topk_ws(uint64_t n, uint64_t CB, uint32_t k)
+// lists_prepass: the pre-pass keeps wave lists (wide score codes), which need
+// the partial area; the selection pre-pass writes the thresholds directly.
+TopkWs topk_ws(uint64_t n, uint64_t CB, uint32_t k, bool lists_prepass)
 {
     TopkWs w{};
     w.cap = topk_cap(n, CB, k);
@@ -190,7 +192,7 @@ TopkWs topk_ws(uint64_t n, uint64_t CB, uint32_t k)
     w.thr = take(8 * n);
     w.cnt = take(4 * n);
     w.ovf = take(4 + 4 * n);
-    w.partial = take(8 * n * (uint64_t)query_lists(1) * (k + 1));
+    w.partial = take(lists_prepass ? 8 * n * (uint64_t)query_lists(1) * (k + 1) : 0);
     w.lists = take(8 * n * (uint64_t)w.cap);
     w.total = o;
     return w;
@@ -685,7 +687,7 @@ int nw_topk_workspace_bytes(const nw_vocab *v, uint32_t k, uint64_t *bytes)
 {
     if (!v || !bytes) return fail(NW_EINVAL, "NULL argument");
     if (k < 1 || k > 63) return fail(NW_EINVAL, "k = %u outside 1..63", k);
-    *bytes = topk_ws(v->n, (uint64_t)v->dev.CB, k).total;
+    *bytes = topk_ws(v->n, (uint64_t)v->dev.CB, k, !probe_thr_applies(v->dev)).total;
     return ok();
 }
 
@@ -700,7 +702,7 @@ int check_topk_args(const nw_vocab *v, uint32_t k, const int16_t *d_score, const
     if (!v->symmetric) return fail(NW_EINVAL, "all-pairs scoring needs a symmetric similarity matrix");
     if (v->max_len > (uint32_t)kMaxLen)
         return fail(NW_EINVAL, "top-k supports words of at most %d symbols (this dictionary has %u)", kMaxLen, v->max_len);
-    const TopkWs W = topk_ws(v->n, (uint64_t)v->dev.CB, k);
+    const TopkWs W = topk_ws(v->n, (uint64_t)v->dev.CB, k, !probe_thr_applies(v->dev));
     if (v->n > 0 && (!d_score || !d_index)) return fail(NW_EINVAL, "d_score / d_index is NULL");
     if (!d_ws || (uintptr_t)d_ws % 256) return fail(NW_EINVAL, "d_ws must be a 256-byte aligned device pointer");
     if (ws_bytes < W.total)
@@ -715,7 +717,7 @@ int topk_enqueue(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_ind
                  hipStream_t st)
 {
     const uint64_t n = v->n;
-    const TopkWs W = topk_ws(n, (uint64_t)v->dev.CB, k);
+    const TopkWs W = topk_ws(n, (uint64_t)v->dev.CB, k, !probe_thr_applies(v->dev));
     const DevVocab &D = v->dev;
     const int nbins = v->hi - v->lo + 1;
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
@@ -791,7 +793,7 @@ int topk_enqueue(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_ind
 int topk_finish(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_index, void *d_ws, hipStream_t st)
 {
     const uint64_t n = v->n;
-    const TopkWs W = topk_ws(n, (uint64_t)v->dev.CB, k);
+    const TopkWs W = topk_ws(n, (uint64_t)v->dev.CB, k, !probe_thr_applies(v->dev));
     nw_vocab *vm = const_cast<nw_vocab *>(v);
     const DevVocab &D = v->dev;
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
