@@ -74,13 +74,33 @@ __global__ __launch_bounds__(kThreads) void k_query_tiled(QueryArgs Q)
                           role);
         __syncthreads();
         uint64_t list0 = 0, list1 = 0, thr0 = 0, thr1 = 0;
-        for (int64_t base = c0 + wave * 64; base < c1; base += kThreads) {
-            const int64_t slot = base + lane;
-            const int lb = Q.C.len[slot];
+        // the next step's column word is loaded while this step's DP and
+        // list offers run (a split is a few steps, so load latency would
+        // otherwise dominate a lightly loaded GPU)
+        int64_t base = c0 + wave * 64;
+        int lb_n = 0;
+        int32_t d_n = -1;
+        uint32_t bw_n[kWordBytes / 4];
+        if (base < c1) {
+            lb_n = Q.C.len[base + lane];
+            d_n = Q.C.orig[base + lane];
+            load_word(bw_n, Q.C.sym + (base + lane) * kWordBytes);
+        }
+        for (; base < c1; base += kThreads) {
+            const int lb = lb_n;
+            const int32_t d = d_n;
+            uint32_t bw[kWordBytes / 4];
+#pragma unroll
+            for (int q = 0; q < kWordBytes / 4; ++q) bw[q] = bw_n[q];
+            const int64_t nx = base + kThreads + lane;
+            if (base + kThreads < c1) {
+                lb_n = Q.C.len[nx];
+                d_n = Q.C.orig[nx];
+                load_word(bw_n, Q.C.sym + nx * kWordBytes);
+            }
             const int lbmax_w = __builtin_amdgcn_readlane(lb, 63);
-            const int32_t d = Q.C.orig[slot];
             int s0, s1;
-            pair_scores<LA>(Q.C.sym + slot * kWordBytes, lb, lbmax_w, prof, Q.gap, s0, s1);
+            pair_scores_regs<LA>(bw, lb, lbmax_w, prof, Q.gap, s0, s1);
             const uint64_t key0 = d >= 0 ? nb_key(s0, Q.lo, (uint32_t)d) : 0;
             const uint64_t key1 = d >= 0 ? nb_key(s1, Q.lo, (uint32_t)d) : 0;
             wl_offer(list0, thr0, key0, Q.k, lane);
@@ -114,6 +134,25 @@ __global__ __launch_bounds__(kThreads) void k_query_tiled(QueryArgs Q)
 }
 
 #ifdef NW_LAUNCH_TU   // non-template kernels: compiled in the launcher unit only
+// Offer the keys src[b0 .. b1) to a wave list (whole wavefront), loading them
+// eight per lane at a time so that one load latency covers 512 keys.
+__device__ __forceinline__ void offer_range(uint64_t &list, uint64_t &t, const uint64_t *src, int b0, int b1, int kout,
+                                            int lane)
+{
+    constexpr int kBatch = 8;
+    for (int base = b0; base < b1; base += 64 * kBatch) {
+        uint64_t key[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const int i = base + q * 64 + lane;
+            key[q] = i < b1 ? src[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+            if (base + q * 64 < b1) wl_offer(list, t, key[q], kout, lane);
+    }
+}
+
 // One wavefront per row: merge P sorted lists of kin keys into the top kout.
 // Writes scores/indices (padding INT16_MIN / -1) when score != NULL and the
 // key of rank `rank` (0 when the list is shorter) to thr when thr != NULL.
@@ -126,11 +165,7 @@ __global__ __launch_bounds__(256) void k_merge_lists(const uint64_t *partial, in
     const uint64_t *src = partial + row * (int64_t)P * kin;
     const int total = P * kin;
     uint64_t list = 0, t = 0;
-    for (int base = 0; base < total; base += 64) {
-        const int i = base + lane;
-        const uint64_t key = i < total ? src[i] : 0;
-        wl_offer(list, t, key, kout, lane);
-    }
+    offer_range(list, t, src, 0, total, kout, lane);
     if (score != nullptr && lane < kout) {
         score[row * kout + lane] = list ? (int16_t)key_score(list, lo) : (int16_t)-32768;
         index[row * kout + lane] = list ? key_index(list) : -1;
@@ -155,10 +190,7 @@ __global__ __launch_bounds__(256) void k_merge_lists_wg(const uint64_t *partial,
     const int per = (total + 3) / 4;
     const int b0 = min(total, wave * per), b1 = min(total, b0 + per);
     uint64_t list = 0, t = 0;
-    for (int base = b0; base < b1; base += 64) {
-        const int i = base + lane;
-        wl_offer(list, t, i < b1 ? src[i] : 0, kout, lane);
-    }
+    offer_range(list, t, src, b0, b1, kout, lane);
     if (lane < kout) quarter[wave * kout + lane] = list;
     __syncthreads();
     if (wave != 0) return;
