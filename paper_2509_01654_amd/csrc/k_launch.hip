@@ -455,9 +455,10 @@ hipError_t launch_topk_main(const DevVocab &V, const TopkArgs &T, hipStream_t st
         if (!plain_epilogue_only() && topk_code_applies(V, T, LA)) {
             // score codes within [0, 1024), the histogram in LDS below 64 KiB
             Tc.hist_in_lds = T.hist != nullptr;
+            Tc.wt_in_lds = topk_code_wt_in_lds(V, T, LA);
             void *args[] = {&Vc, &Tc};
             e = launch_dyn(tab.topk_code[LA], dim3(nblk_pairs),
-                           topk_code_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB), fork, args);
+                           topk_code_lds_bytes(LA, V.alphabet, T.nbins, Tc.hist_in_lds, V.CB, Tc.wt_in_lds), fork, args);
         } else {
             // the histogram copies go to LDS when they fit beside the profiles
             // (large alphabets with wide score ranges add to global bins instead)

@@ -28,6 +28,7 @@ struct TopkArgs {
     int lo;                     // lowest score (key and bin origin)
     int nbins;
     int hist_in_lds;            // 1: per-workgroup LDS histogram copies; 0: global atomics
+    int wt_in_lds;              // score-code kernel: 1 stages the similarity table in LDS
     // block pairs of this launch: (b - r) mod phase_mod in [phase_lo, phase_hi]
     int phase_mod, phase_lo, phase_hi;
 };

@@ -52,21 +52,24 @@ __host__ __device__ constexpr uint32_t chunk_bytes(int LA)
 {
     return 2u * kChunkPairs * (chunk_sym_bytes(LA) + 8u);
 }
-// The similarity table w(x, y) is staged in LDS for alphabets up to 48
-// symbols (4.5 KiB); larger tables are read from global memory, where they
-// stay cached, so that they do not cost workgroups per CU.
+// The similarity table w(x, y) may be staged in LDS for alphabets up to 48
+// symbols (4.5 KiB), where the build of the row-pair profiles reads it; the
+// launcher stages it only when that costs no workgroup per CU (topk_code_wt_in_lds).
+// Otherwise it is read from global memory, where it stays cached.
 constexpr int kLdsWtabMaxAlphabet = 48;
-__host__ __device__ constexpr uint32_t wtab_lds_bytes(int alphabet)
+__host__ __device__ constexpr uint32_t wtab_lds_bytes(int alphabet, int in_lds)
 {
-    return alphabet <= kLdsWtabMaxAlphabet ? (((uint32_t)alphabet * (uint32_t)alphabet * 2u + 15u) & ~15u) : 0u;
+    return in_lds && alphabet <= kLdsWtabMaxAlphabet ? (((uint32_t)alphabet * (uint32_t)alphabet * 2u + 15u) & ~15u)
+                                                     : 0u;
 }
 // LDS of k_topk_code: two profile buffers, the histogram copies, 4 bytes of
 // metadata per column slot, the longest length of each group of 64 slots, the
 // similarity table, two row-pair chunks and the candidate pools.
-__host__ __device__ constexpr uint32_t topk_code_lds_bytes(int LA, int alphabet, int nbins, int has_hist, int CB)
+__host__ __device__ constexpr uint32_t topk_code_lds_bytes(int LA, int alphabet, int nbins, int has_hist, int CB,
+                                                        int wt_in_lds)
 {
     return 2u * topk_code_profile_bytes(LA, topk_code_pairs(LA), alphabet) + topk_hist_bytes(nbins, has_hist) +
-           4u * (uint32_t)CB + (((uint32_t)CB / 64u + 15u) & ~15u) + wtab_lds_bytes(alphabet) +
+           4u * (uint32_t)CB + (((uint32_t)CB / 64u + 15u) & ~15u) + wtab_lds_bytes(alphabet, wt_in_lds) +
            2u * chunk_bytes(LA) + topk_pool_bytes();
 }
 
@@ -78,7 +81,17 @@ __host__ __device__ inline bool topk_code_applies(const DevVocab &V, const TopkA
     return T.lo <= V.lo && V.hi - T.lo < 1024 && (T.hist == nullptr || T.nbins <= kCodeMaxBins) &&
            2u * topk_code_profile_bytes(LA, topk_code_pairs(LA), V.alphabet) +
                    topk_hist_bytes(T.nbins, T.hist != nullptr) <= 65536u &&
-           topk_code_lds_bytes(LA, V.alphabet, T.nbins, T.hist != nullptr, V.CB) <= kMaxLdsBytes;
+           topk_code_lds_bytes(LA, V.alphabet, T.nbins, T.hist != nullptr, V.CB, 0) <= kMaxLdsBytes;
+}
+
+// Stage the similarity table in LDS when the alphabet allows it and the LDS
+// of a workgroup then still admits as many workgroups per CU as without it.
+__host__ __device__ inline bool topk_code_wt_in_lds(const DevVocab &V, const TopkArgs &T, int LA)
+{
+    if (V.alphabet > kLdsWtabMaxAlphabet) return false;
+    const int h = T.hist != nullptr;
+    return kMaxLdsBytes / topk_code_lds_bytes(LA, V.alphabet, T.nbins, h, V.CB, 1) ==
+           kMaxLdsBytes / topk_code_lds_bytes(LA, V.alphabet, T.nbins, h, V.CB, 0);
 }
 
 // The code of threshold score ts: kCodeOrigin + ts - lo, clamped to [0, kCodeNever].
@@ -140,7 +153,7 @@ void k_topk_code(DevVocab V, TopkArgs T)
     uint32_t *meta = reinterpret_cast<uint32_t *>(lds + meta_off);
     uint8_t *gmax = lds + meta_off + 4u * (uint32_t)CB;
     uint16_t *wt_lds = reinterpret_cast<uint16_t *>(gmax + (((uint32_t)CB / 64u + 15u) & ~15u));
-    uint8_t *chunks = reinterpret_cast<uint8_t *>(wt_lds) + wtab_lds_bytes(A);
+    uint8_t *chunks = reinterpret_cast<uint8_t *>(wt_lds) + wtab_lds_bytes(A, T.wt_in_lds);
     constexpr uint32_t SW = chunk_sym_bytes(LA);
     CandPool pool;
     {
@@ -160,7 +173,7 @@ void k_topk_code(DevVocab V, TopkArgs T)
         meta[i] = kbits | (tj << 16);
         if ((i & 63) == 63) gmax[i >> 6] = (uint8_t)lb;
     }
-    const bool wt_staged = A <= kLdsWtabMaxAlphabet;
+    const bool wt_staged = T.wt_in_lds && A <= kLdsWtabMaxAlphabet;
     if (wt_staged)
         for (int i = tid; i < A * A; i += kThreads) wt_lds[i] = V.wtab[i];
     const uint16_t *wt = wt_staged ? wt_lds : V.wtab;

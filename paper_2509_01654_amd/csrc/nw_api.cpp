@@ -62,13 +62,15 @@ int refuse_capture(hipStream_t stream, const char *call)
 // 24-symbol words, blocks of 2048 from 32k words on (50k-word triangle
 // 3.15 -> 2.98 ms); with longer words 1024 up to 131k words (2048 made the
 // batched workload's 40k..100k-word dictionaries of words up to 31..48
-// symbols 7 % slower).
+// symbols 7 % slower).  Past 131k words, blocks of 3072: the 600k-word top-k
+// main pass took 420 ms with 2048, 413 with 2560, 407 with 3072, 410 with
+// 3584 and 417 with 4096 (the 50k-word triangle is slower with 3072).
 int choose_block(uint64_t n, uint32_t max_len)
 {
     if (n <= 16384) return 256;
     if (n <= 32768) return 1024;
-    if (n <= 131072 && max_len > 24) return 1024;
-    return 2048;
+    if (n <= 131072) return max_len > 24 ? 1024 : 2048;
+    return 3072;
 }
 
 
@@ -762,7 +764,7 @@ int topk_enqueue(const nw_vocab *v, uint32_t k, int16_t *d_score, int32_t *d_ind
     // an eighth of its partners, spread over the whole dictionary -- then each
     // word's threshold is raised to the k-th best of its candidates so far,
     // and the remaining block pairs emit far fewer candidates.
-    TopkArgs T;
+    TopkArgs T{};
     T.thr = thr;
     T.cnt = cnt;
     T.lists = lists;
