@@ -134,25 +134,6 @@ __global__ __launch_bounds__(kThreads) void k_query_tiled(QueryArgs Q)
 }
 
 #ifdef NW_LAUNCH_TU   // non-template kernels: compiled in the launcher unit only
-// Offer the keys src[b0 .. b1) to a wave list (whole wavefront), loading them
-// eight per lane at a time so that one load latency covers 512 keys.
-__device__ __forceinline__ void offer_range(uint64_t &list, uint64_t &t, const uint64_t *src, int b0, int b1, int kout,
-                                            int lane)
-{
-    constexpr int kBatch = 8;
-    for (int base = b0; base < b1; base += 64 * kBatch) {
-        uint64_t key[kBatch];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            const int i = base + q * 64 + lane;
-            key[q] = i < b1 ? src[i] : 0;
-        }
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q)
-            if (base + q * 64 < b1) wl_offer(list, t, key[q], kout, lane);
-    }
-}
-
 // One wavefront per row: merge P sorted lists of kin keys into the top kout.
 // Writes scores/indices (padding INT16_MIN / -1) when score != NULL and the
 // key of rank `rank` (0 when the list is shorter) to thr when thr != NULL.

@@ -273,11 +273,7 @@ __global__ __launch_bounds__(256) void k_tighten(const uint32_t *cnt, const uint
     if (m < k) return;
     const uint64_t *src = lists + w * (int64_t)cap;
     uint64_t list = 0, t = 0;
-    for (int base = 0; base < m; base += 64) {
-        const int i = base + lane;
-        const uint64_t key = i < m ? src[i] : 0;
-        wl_offer(list, t, key, k, lane);
-    }
+    offer_range(list, t, src, 0, m, k, lane);
     const uint64_t kth = readlane64(list, k - 1);
     if (lane == 0 && kth > thr[w]) thr[w] = kth;
 }
@@ -299,11 +295,7 @@ __global__ __launch_bounds__(256) void k_select(const uint32_t *cnt, const uint6
     const int m = (int)(c < cap ? c : cap);
     const uint64_t *src = lists + w * (int64_t)cap;
     uint64_t list = 0, t = 0;
-    for (int base = 0; base < m; base += 64) {
-        const int i = base + lane;
-        const uint64_t key = i < m ? src[i] : 0;
-        wl_offer(list, t, key, k, lane);
-    }
+    offer_range(list, t, src, 0, m, k, lane);
     if (lane < k) {
         score[w * k + lane] = list ? (int16_t)key_score(list, lo) : (int16_t)-32768;
         index[w * k + lane] = list ? key_index(list) : -1;
